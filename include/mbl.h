@@ -1,0 +1,203 @@
+/*
+ * mbl.h - C ABI of the MI355X (gfx950) library for nested shift-invert
+ * diagonalization of the periodic random-field Heisenberg chain in the
+ * S^z = 0 sector (Kutsuzawa & Todo, arXiv:2203.09732).
+ *
+ * Model (Sec. I, Eq. (1)):  H = sum_{j=1}^{L} ( S_j . S_{j+1} - h_j S^z_j ),
+ * S_{L+1} = S_1, L even, J = 1. Site j is bit j-1 of a state integer and a set
+ * bit is S^z = +1/2. The sector basis is every L-bit integer with L/2 set bits
+ * in ascending order; index i of an n-vector is the i-th such integer,
+ * n = C(L, L/2).
+ *
+ * Conventions for every entry point:
+ *  - Return value: 0 (MBL_OK) on success; < 0 on error, in which case no
+ *    output has been written and nothing was launched; > 0 is a warning and
+ *    the outputs are valid but best effort (see each call).
+ *    mbl_last_error() gives a message for the last non-OK status on the
+ *    calling thread.
+ *  - Host pointers are named *_host; device pointers *_dev. Device buffers are
+ *    owned by the caller, contiguous, and never freed by the library.
+ *    n-vectors are FP64 unless stated.
+ *  - h_host points to L doubles (the fields h_1..h_L); it is read during the
+ *    call only.
+ *  - stream is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls that return host values synchronize that stream; the others are
+ *    asynchronous with respect to the host.
+ *  - Handles (mbl_basis, mbl_workspace) are created and freed by the library.
+ *    A basis is immutable after creation and may be shared by streams; a
+ *    workspace must not be used by two calls at once.
+ */
+#ifndef MBL_H
+#define MBL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mbl_status;
+enum {
+  MBL_OK = 0,
+  MBL_ERR_ARG = -1,        /* invalid argument; nothing done */
+  MBL_ERR_NOMEM = -2,      /* device or host allocation failed */
+  MBL_ERR_HIP = -3,        /* a HIP runtime call failed */
+  MBL_ERR_NUMERIC = -4,    /* NaN/Inf met in a recurrence */
+  MBL_WARN_NOCONV = 1,     /* iteration limit reached before the tolerance */
+  MBL_WARN_BREAKDOWN = 2   /* Lanczos found an invariant subspace (beta ~ 0) */
+};
+
+/* Arithmetic of the MINRES inner solves. */
+enum {
+  MBL_FP64 = 0,            /* FP64 throughout */
+  MBL_FP32_INNER = 1       /* FP32 MINRES vectors and matvec, FP64 residual
+                              recomputation b - (H - sigma) x and restart;
+                              Lanczos, Ritz values and residual checks FP64 */
+};
+
+/* Diagonal preconditioner M = C C^dagger (Sec. II). */
+enum {
+  MBL_PRECOND_ROW = 0,     /* M = diag(r_i), r_i = 2-norm of row i of H - sigma I
+                              (Eq. (rownorm_preconditioner)) */
+  MBL_PRECOND_JACOBI = 1,  /* M = diag(|a_ii - sigma|); an element equal to 0 is
+                              an argument error at solve time (MBL_ERR_NUMERIC) */
+  MBL_PRECOND_ID = 2       /* M = I */
+};
+
+typedef struct mbl_basis_s* mbl_basis;
+typedef struct mbl_workspace_s* mbl_workspace;
+
+/* ---- basis (Sec. III: dimension C(L, L/2)) --------------------------------
+ * mbl_build_basis: builds the sector tables for an even L, 4 <= L <= 32, on
+ * the current HIP device. lo_bits = number of low bits in the (high, low)
+ * split of a state used by the kernels (0 = library default; else
+ * 1 <= lo_bits <= 13 and lo_bits < L). Errors: MBL_ERR_ARG for odd/out of
+ * range L or lo_bits. Synchronizes stream. */
+mbl_status mbl_build_basis(int L, int lo_bits, void* stream, mbl_basis* out);
+void mbl_basis_free(mbl_basis b);
+/* n = C(L, L/2) */
+mbl_status mbl_basis_dim(mbl_basis b, int64_t* n);
+/* number of low bits of the (high, low) split the basis was built with */
+mbl_status mbl_basis_lo_bits(mbl_basis b, int* lo_bits);
+/* Writes the n sector states (ascending uint32) to states_dev[n]. Async. */
+mbl_status mbl_basis_states(mbl_basis b, uint32_t* states_dev, void* stream);
+/* Index of each of count states (each must be a sector state) into
+ * ranks_dev[count] (int64). A state outside the sector yields -1. Async. */
+mbl_status mbl_basis_rank(mbl_basis b, const uint32_t* states_dev, int64_t count,
+                          int64_t* ranks_dev, void* stream);
+
+/* ---- workspace -------------------------------------------------------------
+ * Device scratch for MINRES (its recurrence vectors) and for up to mmax
+ * Lanczos basis vectors, 0 <= mmax <= 1000 (MBL_ERR_ARG otherwise).
+ * precision selects the MINRES vector type. */
+mbl_status mbl_workspace_create(mbl_basis b, int mmax, int precision, mbl_workspace* ws);
+void mbl_workspace_free(mbl_workspace ws);
+/* Device bytes held by the workspace. */
+mbl_status mbl_workspace_bytes(mbl_workspace ws, int64_t* bytes);
+
+/* ---- y = (H - sigma I) x (Eq. (1); the matrix-vector product inside Alg. 2)
+ * x_dev, y_dev: n doubles, must not overlap. The matrix is never stored:
+ * diagonal and spin-flip elements are generated from the state bits. Async. */
+mbl_status mbl_apply_H(mbl_basis b, const double* h_host, double sigma,
+                       const double* x_dev, double* y_dev, void* stream);
+/* Same product in FP32 storage (diagonal formed in FP64, then rounded). */
+mbl_status mbl_apply_H_f32(mbl_basis b, const double* h_host, double sigma,
+                           const float* x_dev, float* y_dev, void* stream);
+
+/* ---- q = M^{-1} z with the chosen diagonal preconditioner (Sec. II,
+ * Eq. (rownorm_preconditioner)). z_dev, q_dev: n doubles (may alias). Async. */
+mbl_status mbl_precond_apply(mbl_basis b, const double* h_host, double sigma, int precond,
+                             const double* z_dev, double* q_dev, void* stream);
+
+/* ---- preconditioned MINRES for (H - sigma I) x = b (App. A, Alg. 2) --------
+ * rhs_dev: n doubles. x_dev: n doubles, initial guess on entry (x0), solution
+ * on exit. Stops when |phi_k| < tol (phi_k = ||b - A x_k||_{M^{-1}}) or after
+ * kmax iterations (MBL_WARN_NOCONV). With MBL_FP32_INNER the inner solves run
+ * in FP32 and restart from the FP64 residual until its M^{-1}-norm is < tol.
+ * Synchronizes stream. info may be NULL. */
+typedef struct {
+  int64_t iters;       /* MINRES iterations, summed over restarts */
+  int32_t restarts;    /* FP64 residual restarts (0 in MBL_FP64) */
+  double phi;          /* final |phi| (recurrence estimate) */
+  double true_res;     /* ||b - (H - sigma) x||_2 recomputed in FP64 */
+} mbl_minres_info;
+mbl_status mbl_minres_solve(mbl_basis b, const double* h_host, double sigma,
+                            const double* rhs_dev, double* x_dev, double tol, int64_t kmax,
+                            int precision, int precond, mbl_workspace ws,
+                            mbl_minres_info* info, void* stream);
+
+/* ---- shift-invert Lanczos (Sec. II, Alg. 1) with MINRES inner solves --------
+ * Finds the nev eigenpairs of H with eigenvalues closest to sigma. Each step
+ * solves (H - sigma) x = v_k by mbl_minres_solve semantics (minres_tol,
+ * minres_kmax), orthogonalises against v_{k-1}, v_k by the three-term
+ * recurrence and then against all earlier v by two classical Gram-Schmidt
+ * passes, all in FP64 on the device. Stops when all nev selected Ritz pairs
+ * satisfy est_i <= eig_tol * escale and est_i <= gap_tol * gap_i, where est_i
+ * is the shift-invert residual estimate mapped to H, gap_i the distance to
+ * the nearest other Ritz value, and escale = max(|E_min|, |E_max|) if passed
+ * > 0, else a Gershgorin bound on ||H||; or when k = mmax (MBL_WARN_NOCONV)
+ * or beta_{k+1} <= 1e-14 * max|theta| (MBL_WARN_BREAKDOWN). gap_tol <= 0
+ * disables the gap test.
+ * v0_dev: n doubles start vector, or NULL for a seeded one (SplitMix64 of
+ * (seed, i) mapped to a uniform in [-1/2, 1/2)).
+ * Outputs: evals_host[nev] ascending; evecs_dev: n x nev column-major with
+ * leading dimension ld >= n, unit 2-norm, sign arbitrary; resid_host[nev]:
+ * explicit ||H u - lambda u||_2 recomputed in FP64 (may be NULL).
+ * Synchronizes stream. info may be NULL. */
+typedef struct {
+  int32_t steps;          /* Lanczos steps k */
+  int32_t nconv;          /* pairs passing the test */
+  int64_t minres_iters;   /* total MINRES iterations */
+  double max_rel_resid;   /* max_i resid_i / escale */
+  double seconds;         /* wall time of the call */
+} mbl_si_info;
+mbl_status mbl_si_lanczos(mbl_basis b, const double* h_host, double sigma, int nev, int mmax,
+                          double minres_tol, int64_t minres_kmax, double eig_tol,
+                          double gap_tol, double escale, const double* v0_dev, uint64_t seed,
+                          int precision, int precond, mbl_workspace ws,
+                          double* evals_host, double* evecs_dev, int64_t ld,
+                          double* resid_host, mbl_si_info* info, void* stream);
+
+/* ---- twist overlap z = <psi|U_twist|psi> (Sec. III; App. B form
+ * z = sum_alpha c_alpha^2 u_alpha) for nvec real vectors psi_dev (n x nvec,
+ * column-major, leading dimension ld >= n). z_host[2*t] = Re z_t,
+ * z_host[2*t+1] = Im z_t. Vectors are used as given (not renormalised).
+ * Synchronizes stream. */
+mbl_status mbl_twist_expect(mbl_basis b, const double* psi_dev, int64_t ld, int nvec,
+                            double* z_host, void* stream);
+
+/* ---- explicit eigen-residuals ||H psi_t - E_t psi_t||_2 (Alg. 1 output
+ * check), psi_dev n x nvec (ld >= n), E_host[nvec], resid_host[nvec].
+ * Synchronizes stream. */
+mbl_status mbl_eig_residual(mbl_basis b, const double* h_host, const double* E_host,
+                            const double* psi_dev, int64_t ld, int nvec,
+                            double* resid_host, void* stream);
+
+/* ---- sigma = (E_min + E_max) / 2 (Sec. IV A) by Lanczos on H with full
+ * reorthogonalisation; E_min, E_max converge to rel_tol * max(|E|).
+ * mmax bounds the steps (0 = default 300). Synchronizes stream. */
+mbl_status mbl_sigma_midpoint(mbl_basis b, const double* h_host, double rel_tol, int mmax,
+                              double* emin, double* emax, double* sigma, void* stream);
+
+/* ---- small device helpers used by the bindings and tests ---------------- */
+/* out_host = sum_i x_i * y_i over n doubles, reduced in a fixed order. */
+mbl_status mbl_dot(int64_t n, const double* x_dev, const double* y_dev, double* out_host,
+                   void* stream);
+
+/* Host-only: eigen-decomposition of the k x k symmetric tridiagonal T_k of
+ * Alg. 1 (diagonal alpha[k], off-diagonal beta[k-1]) by implicit QL
+ * iterations. evals_host[k] ascending; evecs_host k x k column-major, column i
+ * for evals_host[i]. Uses no device. MBL_ERR_NUMERIC if an eigenvalue needs
+ * more than 60 iterations. */
+mbl_status mbl_tridiag_eig(int k, const double* alpha_host, const double* beta_host,
+                           double* evals_host, double* evecs_host);
+
+/* Message for the last non-OK status on this thread ("" if none). */
+const char* mbl_last_error(void);
+/* Library version string. */
+const char* mbl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MBL_H */

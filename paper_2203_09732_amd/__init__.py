@@ -1,0 +1,341 @@
+"""Python binding of libmbl.so, the gfx950 library for nested shift-invert
+diagonalization of the random-field Heisenberg chain (arXiv:2203.09732).
+
+This module only marshals arguments: device buffers are torch tensors on the
+current HIP device (``tensor.data_ptr()``), streams are
+``torch.cuda.current_stream().cuda_stream``, and every step of the method
+runs in the library's kernels. Importing fails if libmbl.so has not been
+built (``python -m paper_2203_09732_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmbl.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -m paper_2203_09732_amd.build` "
+        "(hipcc, gfx950). There is no fallback implementation.")
+
+lib = C.CDLL(LIB_PATH)
+
+OK, ERR_ARG, ERR_NOMEM, ERR_HIP, ERR_NUMERIC = 0, -1, -2, -3, -4
+WARN_NOCONV, WARN_BREAKDOWN = 1, 2
+FP64, FP32_INNER = 0, 1
+PRECOND = {"row": 0, "jacobi": 1, "id": 2}
+PRECISION = {"fp64": FP64, "fp32_inner": FP32_INNER}
+
+_vp, _dp, _i32, _i64, _u64, _d = C.c_void_p, C.POINTER(C.c_double), C.c_int32, C.c_int64, C.c_uint64, C.c_double
+
+
+class MinresInfo(C.Structure):
+    _fields_ = [("iters", C.c_int64), ("restarts", C.c_int32), ("phi", C.c_double),
+                ("true_res", C.c_double)]
+
+
+class SiInfo(C.Structure):
+    _fields_ = [("steps", C.c_int32), ("nconv", C.c_int32), ("minres_iters", C.c_int64),
+                ("max_rel_resid", C.c_double), ("seconds", C.c_double)]
+
+
+def _sig(name, res, args):
+    f = getattr(lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_sig("mbl_last_error", C.c_char_p, [])
+_sig("mbl_version", C.c_char_p, [])
+_sig("mbl_build_basis", _i32, [C.c_int, C.c_int, _vp, C.POINTER(_vp)])
+_sig("mbl_basis_free", None, [_vp])
+_sig("mbl_basis_dim", _i32, [_vp, C.POINTER(C.c_int64)])
+_sig("mbl_basis_lo_bits", _i32, [_vp, C.POINTER(C.c_int)])
+_sig("mbl_basis_states", _i32, [_vp, _vp, _vp])
+_sig("mbl_basis_rank", _i32, [_vp, _vp, _i64, _vp, _vp])
+_sig("mbl_workspace_create", _i32, [_vp, C.c_int, C.c_int, C.POINTER(_vp)])
+_sig("mbl_workspace_free", None, [_vp])
+_sig("mbl_workspace_bytes", _i32, [_vp, C.POINTER(C.c_int64)])
+_sig("mbl_apply_H", _i32, [_vp, _dp, _d, _vp, _vp, _vp])
+_sig("mbl_apply_H_f32", _i32, [_vp, _dp, _d, _vp, _vp, _vp])
+_sig("mbl_precond_apply", _i32, [_vp, _dp, _d, C.c_int, _vp, _vp, _vp])
+_sig("mbl_minres_solve", _i32, [_vp, _dp, _d, _vp, _vp, _d, _i64, C.c_int, C.c_int, _vp,
+                                C.POINTER(MinresInfo), _vp])
+_sig("mbl_si_lanczos", _i32, [_vp, _dp, _d, C.c_int, C.c_int, _d, _i64, _d, _d, _d, _vp, _u64,
+                              C.c_int, C.c_int, _vp, _dp, _vp, _i64, _dp, C.POINTER(SiInfo), _vp])
+_sig("mbl_twist_expect", _i32, [_vp, _vp, _i64, C.c_int, _dp, _vp])
+_sig("mbl_eig_residual", _i32, [_vp, _dp, _dp, _vp, _i64, C.c_int, _dp, _vp])
+_sig("mbl_sigma_midpoint", _i32, [_vp, _dp, _d, C.c_int, _dp, _dp, _dp, _vp])
+_sig("mbl_dot", _i32, [_i64, _vp, _vp, _dp, _vp])
+_sig("mbl_tridiag_eig", _i32, [C.c_int, _dp, _dp, _dp, _dp])
+
+
+class MblError(RuntimeError):
+    def __init__(self, status, where):
+        msg = lib.mbl_last_error().decode()
+        super().__init__(f"{where}: status {status}: {msg}")
+        self.status = status
+
+
+def _check(st, where, warn_ok=True):
+    if st < 0 or (st > 0 and not warn_ok):
+        raise MblError(st, where)
+    return st
+
+
+def version() -> str:
+    return lib.mbl_version().decode()
+
+
+def _f64(a):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    return a, a.ctypes.data_as(_dp)
+
+
+def _stream(stream=None):
+    if stream is not None:
+        return C.c_void_p(stream)
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def _need_cuda(t, dtype, n=None, name="tensor"):
+    import torch
+    if not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor on the GPU")
+    if n is not None and t.numel() < n:
+        raise ValueError(f"{name} has {t.numel()} elements, need {n}")
+    return torch
+
+
+class Basis:
+    """Sector basis of the S^z = 0 sector of an L-site ring (dim C(L, L/2))."""
+
+    def __init__(self, L: int, lo_bits: int = 0, stream=None):
+        h = C.c_void_p()
+        _check(lib.mbl_build_basis(int(L), int(lo_bits), _stream(stream), C.byref(h)),
+               "mbl_build_basis", warn_ok=False)
+        self._h = h
+        self.L = int(L)
+        n = C.c_int64()
+        _check(lib.mbl_basis_dim(h, C.byref(n)), "mbl_basis_dim")
+        self.n = int(n.value)
+        lb = C.c_int()
+        _check(lib.mbl_basis_lo_bits(h, C.byref(lb)), "mbl_basis_lo_bits")
+        self.lo_bits = int(lb.value)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and lib is not None:
+            try:
+                lib.mbl_basis_free(self._h)
+            except Exception:   # interpreter shutdown
+                pass
+            self._h = None
+
+    def states(self, stream=None):
+        import torch
+        out = torch.empty(self.n, dtype=torch.int32, device="cuda")
+        _check(lib.mbl_basis_states(self._h, _ptr(out), _stream(stream)), "mbl_basis_states")
+        return out.to(torch.int64) & 0xFFFFFFFF
+
+    def rank(self, states, stream=None):
+        import torch
+        s32 = (states.to(torch.int64) & 0xFFFFFFFF).to(torch.int32).contiguous()
+        out = torch.empty(s32.numel(), dtype=torch.int64, device="cuda")
+        _check(lib.mbl_basis_rank(self._h, _ptr(s32), s32.numel(), _ptr(out), _stream(stream)),
+               "mbl_basis_rank")
+        return out
+
+
+class Workspace:
+    def __init__(self, basis: Basis, mmax: int = 0, precision: str = "fp64"):
+        h = C.c_void_p()
+        _check(lib.mbl_workspace_create(basis.handle, int(mmax), PRECISION[precision],
+                                        C.byref(h)), "mbl_workspace_create", warn_ok=False)
+        self._h = h
+        self.basis = basis
+        self.mmax = int(mmax)
+        b = C.c_int64()
+        _check(lib.mbl_workspace_bytes(h, C.byref(b)), "mbl_workspace_bytes")
+        self.bytes = int(b.value)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and lib is not None:
+            try:
+                lib.mbl_workspace_free(self._h)
+            except Exception:   # interpreter shutdown
+                pass
+            self._h = None
+
+
+def apply_H(basis: Basis, h, sigma: float, x, y=None, stream=None):
+    """y = (H - sigma I) x for FP64 or FP32 x."""
+    import torch
+    if x.dtype not in (torch.float64, torch.float32):
+        raise ValueError("x must be float64 or float32")
+    _need_cuda(x, x.dtype, basis.n, "x")
+    if y is None:
+        y = torch.empty_like(x)
+    _need_cuda(y, x.dtype, basis.n, "y")
+    ha, hp = _f64(h)
+    fn = lib.mbl_apply_H if x.dtype == torch.float64 else lib.mbl_apply_H_f32
+    _check(fn(basis.handle, hp, float(sigma), _ptr(x), _ptr(y), _stream(stream)), "mbl_apply_H")
+    return y
+
+
+def precond_apply(basis: Basis, h, sigma: float, z, q=None, kind: str = "row", stream=None):
+    import torch
+    _need_cuda(z, torch.float64, basis.n, "z")
+    if q is None:
+        q = torch.empty_like(z)
+    ha, hp = _f64(h)
+    _check(lib.mbl_precond_apply(basis.handle, hp, float(sigma), PRECOND[kind], _ptr(z), _ptr(q),
+                                 _stream(stream)), "mbl_precond_apply")
+    return q
+
+
+@dataclass
+class SolveInfo:
+    status: int
+    iters: int
+    restarts: int
+    phi: float
+    true_res: float
+
+
+def minres_solve(basis: Basis, h, sigma: float, b, x=None, tol: float = 1e-12,
+                 kmax: int = 10_000_000, precision: str = "fp64", precond: str = "row",
+                 ws: Workspace | None = None, stream=None):
+    """Preconditioned MINRES for (H - sigma) x = b (Alg. 2). Returns (x, info)."""
+    import torch
+    _need_cuda(b, torch.float64, basis.n, "b")
+    if x is None:
+        x = torch.zeros_like(b)
+    _need_cuda(x, torch.float64, basis.n, "x")
+    ws = ws or Workspace(basis, 0, precision)
+    ha, hp = _f64(h)
+    info = MinresInfo()
+    st = lib.mbl_minres_solve(basis.handle, hp, float(sigma), _ptr(b), _ptr(x), float(tol),
+                              int(kmax), PRECISION[precision], PRECOND[precond], ws.handle,
+                              C.byref(info), _stream(stream))
+    _check(st, "mbl_minres_solve")
+    return x, SolveInfo(st, info.iters, info.restarts, info.phi, info.true_res)
+
+
+@dataclass
+class EigResult:
+    status: int
+    evals: np.ndarray
+    evecs: object          # torch (n, nev) view of column-major storage
+    resid: np.ndarray
+    steps: int
+    nconv: int
+    minres_iters: int
+    max_rel_resid: float
+    seconds: float
+
+
+def si_lanczos(basis: Basis, h, sigma: float, nev: int, mmax: int | None = None,
+               minres_tol: float = 1e-12, minres_kmax: int = 10_000_000,
+               eig_tol: float = 1e-10, gap_tol: float = 1e-5, escale: float = 0.0,
+               v0=None, seed: int = 0, precision: str = "fp64", precond: str = "row",
+               ws: Workspace | None = None, stream=None) -> EigResult:
+    """The nev eigenpairs nearest sigma by shift-invert Lanczos (Alg. 1)."""
+    import torch
+    if mmax is None:
+        mmax = min(basis.n, 3 * nev + 40)
+    ws = ws if ws is not None else Workspace(basis, mmax, precision)
+    if v0 is not None:
+        _need_cuda(v0, torch.float64, basis.n, "v0")
+    store = torch.empty((nev, basis.n), dtype=torch.float64, device="cuda")
+    evals = np.zeros(nev)
+    resid = np.zeros(nev)
+    info = SiInfo()
+    ha, hp = _f64(h)
+    st = lib.mbl_si_lanczos(basis.handle, hp, float(sigma), int(nev), int(mmax), float(minres_tol),
+                            int(minres_kmax), float(eig_tol), float(gap_tol), float(escale),
+                            _ptr(v0) if v0 is not None else None, int(seed) & (2**64 - 1),
+                            PRECISION[precision], PRECOND[precond], ws.handle,
+                            evals.ctypes.data_as(_dp), _ptr(store), basis.n,
+                            resid.ctypes.data_as(_dp), C.byref(info), _stream(stream))
+    _check(st, "mbl_si_lanczos")
+    return EigResult(st, evals, store.t(), resid, info.steps, info.nconv, info.minres_iters,
+                     info.max_rel_resid, info.seconds)
+
+
+def twist_expect(basis: Basis, psi, stream=None) -> np.ndarray:
+    """z_t = <psi_t|U_twist|psi_t> for the columns of psi (n,) or (n, nvec)."""
+    import torch
+    if psi.dim() == 1:
+        psi = psi[:, None]
+    # column-major storage with leading dimension n
+    store = psi.t().contiguous() if not psi.t().is_contiguous() else psi.t()
+    _need_cuda(store, torch.float64, None, "psi")
+    nvec = store.shape[0]
+    z = np.zeros(2 * nvec)
+    _check(lib.mbl_twist_expect(basis.handle, _ptr(store), basis.n, nvec, z.ctypes.data_as(_dp),
+                                _stream(stream)), "mbl_twist_expect")
+    return z[0::2] + 1j * z[1::2]
+
+
+def eig_residual(basis: Basis, h, E, psi, stream=None) -> np.ndarray:
+    import torch
+    if psi.dim() == 1:
+        psi = psi[:, None]
+    store = psi.t().contiguous() if not psi.t().is_contiguous() else psi.t()
+    _need_cuda(store, torch.float64, None, "psi")
+    nvec = store.shape[0]
+    Ea, Ep = _f64(np.atleast_1d(E))
+    out = np.zeros(nvec)
+    ha, hp = _f64(h)
+    _check(lib.mbl_eig_residual(basis.handle, hp, Ep, _ptr(store), basis.n, nvec,
+                                out.ctypes.data_as(_dp), _stream(stream)), "mbl_eig_residual")
+    return out
+
+
+def sigma_midpoint(basis: Basis, h, rel_tol: float = 1e-12, mmax: int = 0, stream=None):
+    """(E_min, E_max, sigma = (E_min + E_max)/2)."""
+    ha, hp = _f64(h)
+    lo, hi, sg = C.c_double(), C.c_double(), C.c_double()
+    _check(lib.mbl_sigma_midpoint(basis.handle, hp, float(rel_tol), int(mmax), C.byref(lo),
+                                  C.byref(hi), C.byref(sg), _stream(stream)), "mbl_sigma_midpoint")
+    return lo.value, hi.value, sg.value
+
+
+def dot(x, y, stream=None) -> float:
+    import torch
+    _need_cuda(x, torch.float64, None, "x")
+    _need_cuda(y, torch.float64, x.numel(), "y")
+    out = C.c_double()
+    _check(lib.mbl_dot(x.numel(), _ptr(x), _ptr(y), C.byref(out), _stream(stream)), "mbl_dot")
+    return out.value
+
+
+def tridiag_eig(alpha, beta):
+    """Host-only eigen-decomposition of the Lanczos tridiagonal T_k."""
+    a, ap = _f64(alpha)
+    k = a.shape[0]
+    b, bp = _f64(beta if k > 1 else np.zeros(1))
+    w = np.zeros(k)
+    V = np.zeros(k * k)
+    _check(lib.mbl_tridiag_eig(k, ap, bp, w.ctypes.data_as(_dp), V.ctypes.data_as(_dp)),
+           "mbl_tridiag_eig", warn_ok=False)
+    return w, V.reshape(k, k).T

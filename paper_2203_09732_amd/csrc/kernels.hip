@@ -1,0 +1,509 @@
+// Row kernels of the matrix-free Hamiltonian (Eq. (1)) on gfx950, and the
+// dense vector helpers around them.
+//
+// Work decomposition. A state a = (hi << nlo) | lo. Rows sharing hi are one
+// contiguous block; a chunk is up to 64 consecutive rows of one block and is
+// processed by one wavefront, one row per lane. Inside a wavefront hi is
+// uniform, so everything that depends on hi alone (block offsets of the
+// neighbour blocks, which high bonds are antiparallel) is scalar work, and a
+// hop on a bond inside the high bits reads a contiguous run of x from the
+// neighbour block: a coalesced load. Hops on bonds inside the low bits stay
+// in the same block (a few KB, cache resident); their targets come from the
+// low-pattern rank table held in LDS. The two bonds that cross the split (the
+// one between bit nlo-1 and bit nlo, and the periodic bond between bit L-1
+// and bit 0) change the popcount of both halves and use both tables.
+//
+// Diagonal: a_aa - sigma = L/4 - N_anti/2 + (1/2) sum_j h_j - F(a) - sigma,
+// where N_anti = popcount(a xor rotl_L(a, 1)) counts antiparallel bonds and
+// F(a) = sum of h_j over set bits, summed from a per-nibble table in LDS.
+//
+// Reductions are per-workgroup partial sums written in a fixed order and
+// reduced again in a fixed order, so results are bitwise reproducible.
+#include "mbl_internal.h"
+
+namespace mbl {
+
+// ---------------------------------------------------------------------------
+// small device helpers
+
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Sum over the workgroup; the result is returned to every thread. red must
+// hold one double per wave. Fixed order: lanes by butterfly, then waves 0..3.
+__device__ __forceinline__ double block_sum_all(double v, double* red) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < kWavesPerWG; ++w) s += red[w];
+  return s;
+}
+
+struct RowTables {
+  const double* lut;       // nibble field table, 16 entries per nibble
+  double* red;             // reduction scratch
+  const uint16_t* rank;    // lo_rank in LDS
+  const uint16_t* state;   // lo_state in LDS
+};
+
+constexpr int kLdsLut = 128;   // doubles (8 nibbles x 16)
+constexpr int kLdsRed = 8;     // doubles
+
+__device__ __forceinline__ RowTables setup_tables(const DevBasis& B, const FieldArgs& F,
+                                                  unsigned char* smem) {
+  double* lut = reinterpret_cast<double*>(smem);
+  double* red = lut + kLdsLut;
+  uint16_t* rank = reinterpret_cast<uint16_t*>(red + kLdsRed);
+  uint16_t* state = rank + (1u << B.nlo);
+  const int nnib = (B.L + 3) >> 2;
+  for (int t = threadIdx.x; t < nnib * 16; t += blockDim.x) {
+    const int k = t >> 4, v = t & 15;
+    double acc = 0.0;
+    for (int b = 0; b < 4; ++b) {
+      const int site = 4 * k + b;
+      if (site < B.L && ((v >> b) & 1)) acc += F.h[site];
+    }
+    lut[t] = acc;
+  }
+  const int words = (1 << B.nlo) >> 1;   // two uint16 per word, nlo >= 1
+  const uint32_t* gr = reinterpret_cast<const uint32_t*>(B.lo_rank);
+  const uint32_t* gs = reinterpret_cast<const uint32_t*>(B.lo_state);
+  uint32_t* sr = reinterpret_cast<uint32_t*>(rank);
+  uint32_t* ss = reinterpret_cast<uint32_t*>(state);
+  for (int t = threadIdx.x; t < words; t += blockDim.x) {
+    sr[t] = gr[t];
+    ss[t] = gs[t];
+  }
+  return RowTables{lut, red, rank, state};
+}
+
+// a_aa - sigma and the number of antiparallel bonds of state a.
+__device__ __forceinline__ double row_diag(const DevBasis& B, const FieldArgs& F,
+                                           const RowTables& t, uint32_t a, int& nanti) {
+  const uint32_t mask = (B.L == 32) ? 0xffffffffu : ((1u << B.L) - 1u);
+  const uint32_t rot = ((a << 1) | (a >> (B.L - 1))) & mask;
+  nanti = __popc(a ^ rot);
+  const int nnib = (B.L + 3) >> 2;
+  double f = 0.0;
+  for (int k = 0; k < nnib; ++k) f += t.lut[(k << 4) + ((a >> (4 * k)) & 15u)];
+  return F.c0 - 0.5 * (double)nanti - f;
+}
+
+// sum of x over the states reached by one spin swap on an antiparallel bond
+template <typename T>
+__device__ __forceinline__ double row_offdiag(const DevBasis& B, const RowTables& t,
+                                              const T* __restrict__ x, uint32_t hi, uint32_t lo,
+                                              uint32_t j, uint32_t block0) {
+  const int nlo = B.nlo, nhi = B.nhi;
+  const T* xb = x + block0;
+  double off = 0.0;
+  // bonds inside the low bits: same block, target from the LDS rank table
+  for (int b = 0; b + 1 < nlo; ++b) {
+    if (((lo >> b) ^ (lo >> (b + 1))) & 1u) off += (double)xb[t.rank[lo ^ (3u << b)]];
+  }
+  // bond between bit nlo-1 and bit nlo
+  {
+    const uint32_t hb = uni(B.hi_off[hi ^ 1u]);
+    if (((lo >> (nlo - 1)) ^ hi) & 1u)
+      off += (double)x[(size_t)hb + t.rank[lo ^ (1u << (nlo - 1))]];
+  }
+  // bonds inside the high bits: uniform over the wave, contiguous loads
+  for (int b = 0; b + 1 < nhi; ++b) {
+    if (((hi >> b) ^ (hi >> (b + 1))) & 1u) {
+      const uint32_t hb = uni(B.hi_off[hi ^ (3u << b)]);
+      off += (double)x[(size_t)hb + j];
+    }
+  }
+  // periodic bond between bit L-1 and bit 0
+  {
+    const uint32_t hb = uni(B.hi_off[hi ^ (1u << (nhi - 1))]);
+    if (((hi >> (nhi - 1)) ^ lo) & 1u) off += (double)x[(size_t)hb + t.rank[lo ^ 1u]];
+  }
+  return off;
+}
+
+// Iterate this wave's chunks; body(row, hi, lo, j, block0, a) for valid lanes.
+template <typename Body>
+__device__ __forceinline__ void for_rows(const DevBasis& B, const RowTables& t, Body body) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wave = uni(threadIdx.x >> 6);
+  const uint32_t stride = gridDim.x * kWavesPerWG;
+  for (uint32_t c = blockIdx.x * kWavesPerWG + wave; c < (uint32_t)B.nchunks; c += stride) {
+    const uint4 ch = B.chunks[c];
+    const uint32_t hi = uni(ch.x), j0 = uni(ch.y), cnt = uni(ch.z), row0 = uni(ch.w);
+    const uint32_t coff = uni(B.lo_coff[B.half - __popc(hi)]);
+    if (lane < cnt) {
+      const uint32_t j = j0 + lane;
+      const uint32_t lo = t.state[coff + j];
+      body(row0 + lane, hi, lo, j, row0 - j0, (hi << B.nlo) | lo);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// y = (H - sigma) x. MODE 0: plain; 1: partial sums of x.y; 2: partial sums of y.y.
+template <typename T, int MODE>
+__global__ __launch_bounds__(kWG) void k_apply(DevBasis B, FieldArgs F, const T* __restrict__ x,
+                                               T* __restrict__ y, double* __restrict__ partials) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const RowTables t = setup_tables(B, F, smem);
+  __syncthreads();
+  double acc = 0.0;
+  for_rows(B, t, [&](uint32_t row, uint32_t hi, uint32_t lo, uint32_t j, uint32_t block0,
+                     uint32_t a) {
+    int na;
+    const double dsh = row_diag(B, F, t, a, na);
+    const double xi = (double)x[row];
+    const double off = row_offdiag<T>(B, t, x, hi, lo, j, block0);
+    const T yt = (T)(dsh * xi + 0.5 * off);
+    y[row] = yt;
+    if (MODE == 1) acc += xi * (double)yt;
+    if (MODE == 2) acc += (double)yt * (double)yt;
+  });
+  if (MODE != 0) {
+    const double s = block_sum_all(acc, t.red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  }
+}
+
+// p = A q with partial sums of q . p, skipped once the MINRES state is done
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_apply_guarded(DevBasis B, FieldArgs F,
+                                                       const MinresState* __restrict__ S,
+                                                       const T* __restrict__ x, T* __restrict__ y,
+                                                       double* __restrict__ partials) {
+  if (S->done) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const RowTables t = setup_tables(B, F, smem);
+  __syncthreads();
+  double acc = 0.0;
+  for_rows(B, t, [&](uint32_t row, uint32_t hi, uint32_t lo, uint32_t j, uint32_t block0,
+                     uint32_t a) {
+    int na;
+    const double dsh = row_diag(B, F, t, a, na);
+    const double xi = (double)x[row];
+    const double off = row_offdiag<T>(B, t, x, hi, lo, j, block0);
+    const T yt = (T)(dsh * xi + 0.5 * off);
+    y[row] = yt;
+    acc += xi * (double)yt;
+  });
+  const double s = block_sum_all(acc, t.red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// preconditioner value m_i for row kind (Sec. II)
+__device__ __forceinline__ double precond_value(int kind, double dsh, int nanti) {
+  if (kind == MBL_PRECOND_ROW) return sqrt(dsh * dsh + 0.25 * (double)nanti);
+  if (kind == MBL_PRECOND_JACOBI) return fabs(dsh);
+  return 1.0;
+}
+
+__global__ __launch_bounds__(kWG) void k_precond(DevBasis B, FieldArgs F, int kind,
+                                                 const double* z, double* q) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const RowTables t = setup_tables(B, F, smem);
+  __syncthreads();
+  for_rows(B, t, [&](uint32_t row, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t a) {
+    int na;
+    const double dsh = row_diag(B, F, t, a, na);
+    q[row] = z[row] / precond_value(kind, dsh, na);
+  });
+}
+
+// r = rhs - (H - sigma) x, partials[2g] = sum r^2 / m, partials[2g+1] = sum r^2
+__global__ __launch_bounds__(kWG) void k_residual(DevBasis B, FieldArgs F, int kind,
+                                                  const double* __restrict__ rhs,
+                                                  const double* __restrict__ x,
+                                                  double* __restrict__ r,
+                                                  double* __restrict__ partials) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const RowTables t = setup_tables(B, F, smem);
+  __syncthreads();
+  double am = 0.0, a2 = 0.0;
+  for_rows(B, t, [&](uint32_t row, uint32_t hi, uint32_t lo, uint32_t j, uint32_t block0,
+                     uint32_t a) {
+    int na;
+    const double dsh = row_diag(B, F, t, a, na);
+    const double off = row_offdiag<double>(B, t, x, hi, lo, j, block0);
+    const double ri = rhs[row] - (dsh * x[row] + 0.5 * off);
+    r[row] = ri;
+    am += ri * ri / precond_value(kind, dsh, na);
+    a2 += ri * ri;
+  });
+  const double sm = block_sum_all(am, t.red);
+  const double s2 = block_sum_all(a2, t.red);
+  if (threadIdx.x == 0) {
+    partials[2 * blockIdx.x] = sm;
+    partials[2 * blockIdx.x + 1] = s2;
+  }
+}
+
+__global__ __launch_bounds__(kWG) void k_states(DevBasis B, uint32_t* states) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  FieldArgs F{};
+  const RowTables t = setup_tables(B, F, smem);
+  __syncthreads();
+  for_rows(B, t, [&](uint32_t row, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t a) {
+    states[row] = a;
+  });
+}
+
+__global__ __launch_bounds__(kWG) void k_rank(DevBasis B, const uint32_t* states, int64_t count,
+                                              int64_t* ranks) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const uint32_t a = states[i];
+  const uint64_t top = (uint64_t)a >> B.L;
+  int64_t out = -1;
+  if (top == 0 && __popc(a) == B.half) {
+    const uint32_t hi = a >> B.nlo, lo = a & ((1u << B.nlo) - 1u);
+    out = (int64_t)B.hi_off[hi] + B.lo_rank[lo];
+  }
+  ranks[i] = out;
+}
+
+// Twist overlap partial sums. m(a) = 2 sum_{set bits p} (p + 1) - L(L+1)/2,
+// u_a = exp(i pi m / L) from a 2L-entry table.
+struct TwistTables {
+  double c[2 * kMaxL];
+  double s[2 * kMaxL];
+};
+
+__global__ __launch_bounds__(kWG) void k_twist(DevBasis B, TwistTables T, const double* psi,
+                                               int64_t ld, double* partials) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  FieldArgs F{};
+  const RowTables t = setup_tables(B, F, smem);
+  __syncthreads();
+  const double* v = psi + (size_t)blockIdx.y * ld;
+  const int twoL = 2 * B.L;
+  const int base = (B.L * (B.L + 1)) / 2;
+  double are = 0.0, aim = 0.0;
+  for_rows(B, t, [&](uint32_t row, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t a) {
+    int sum = 0;   // sum over set bits of (p + 1)
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      uint32_t w = 0;
+      for (int p = 0; p < 32; ++p)
+        if (((p + 1) >> k) & 1) w |= (1u << p);
+      sum += __popc(a & w) << k;
+    }
+    int m = (2 * sum - base) % twoL;
+    if (m < 0) m += twoL;
+    const double c2 = v[row] * v[row];
+    are += c2 * T.c[m];
+    aim += c2 * T.s[m];
+  });
+  const double sr = block_sum_all(are, t.red);
+  const double si = block_sum_all(aim, t.red);
+  if (threadIdx.x == 0) {
+    const size_t g = (size_t)blockIdx.y * gridDim.x + blockIdx.x;
+    partials[2 * g] = sr;
+    partials[2 * g + 1] = si;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// dense helpers
+
+constexpr int kDenseGrid = 512;
+
+__global__ __launch_bounds__(kWG) void k_dot(int64_t n, const double* __restrict__ x,
+                                             const double* __restrict__ y,
+                                             double* __restrict__ partials) {
+  __shared__ double red[kWavesPerWG];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    acc += x[i] * y[i];
+  const double s = block_sum_all(acc, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+// out[v] = sum_{g < nparts} partials[g * stride + v], one workgroup per v.
+__global__ __launch_bounds__(kWG) void k_reduce(const double* __restrict__ partials, int nparts,
+                                                int stride, double* __restrict__ out) {
+  __shared__ double red[kWavesPerWG];
+  const int v = blockIdx.x;
+  double acc = 0.0;
+  for (int g = threadIdx.x; g < nparts; g += blockDim.x) acc += partials[(size_t)g * stride + v];
+  const double s = block_sum_all(acc, red);
+  if (threadIdx.x == 0) out[v] = s;
+}
+
+__global__ __launch_bounds__(kWG) void k_axpby(int64_t n, double a, const double* __restrict__ x,
+                                               double b, double* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = a * x[i] + b * y[i];
+}
+
+__global__ __launch_bounds__(kWG) void k_scale_copy(int64_t n, double a, const double* __restrict__ x,
+                                                    double* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = a * x[i];
+}
+
+__global__ __launch_bounds__(kWG) void k_fill(int64_t n, double v, double* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = v;
+}
+
+// SplitMix64 (Steele, Lea & Flood 2014) of seed + (i + 1) * golden gamma,
+// top 53 bits mapped to [-1/2, 1/2).
+__global__ __launch_bounds__(kWG) void k_splitmix(int64_t n, uint64_t seed, double* __restrict__ y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    uint64_t z = seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    y[i] = (double)(z >> 11) * 0x1.0p-53 - 0.5;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host launch wrappers
+
+int row_grid(const mbl_basis_s* b) {
+  int g = (b->nchunks + kWavesPerWG - 1) / kWavesPerWG;
+  if (g > kMaxPartials) g = kMaxPartials;
+  if (g < 1) g = 1;
+  return g;
+}
+
+size_t row_lds_bytes(const mbl_basis_s* b) {
+  return (kLdsLut + kLdsRed) * sizeof(double) + 2 * sizeof(uint16_t) * ((size_t)1 << b->nlo);
+}
+
+static int dense_grid(int64_t n) {
+  int64_t g = (n + kWG - 1) / kWG;
+  return (int)(g < 1 ? 1 : (g > kDenseGrid ? kDenseGrid : g));
+}
+
+template <typename T>
+hipError_t launch_apply(const mbl_basis_s* b, const FieldArgs& F, const T* x, T* y, int mode,
+                        double* partials, int* nparts, hipStream_t s) {
+  const int g = row_grid(b);
+  const size_t lds = row_lds_bytes(b);
+  if (nparts) *nparts = g;
+  if (mode == 0)
+    hipLaunchKernelGGL((k_apply<T, 0>), dim3(g), dim3(kWG), lds, s, b->dev(), F, x, y, partials);
+  else if (mode == 1)
+    hipLaunchKernelGGL((k_apply<T, 1>), dim3(g), dim3(kWG), lds, s, b->dev(), F, x, y, partials);
+  else
+    hipLaunchKernelGGL((k_apply<T, 2>), dim3(g), dim3(kWG), lds, s, b->dev(), F, x, y, partials);
+  return hipGetLastError();
+}
+template hipError_t launch_apply<double>(const mbl_basis_s*, const FieldArgs&, const double*,
+                                         double*, int, double*, int*, hipStream_t);
+template hipError_t launch_apply<float>(const mbl_basis_s*, const FieldArgs&, const float*, float*,
+                                        int, double*, int*, hipStream_t);
+
+template <typename T>
+hipError_t launch_minres_apply(const mbl_basis_s* b, const FieldArgs& F, const MinresState* S,
+                               const T* q, T* p, double* partials, hipStream_t s) {
+  hipLaunchKernelGGL((k_apply_guarded<T>), dim3(row_grid(b)), dim3(kWG), row_lds_bytes(b), s,
+                     b->dev(), F, S, q, p, partials);
+  return hipGetLastError();
+}
+template hipError_t launch_minres_apply<double>(const mbl_basis_s*, const FieldArgs&,
+                                                const MinresState*, const double*, double*,
+                                                double*, hipStream_t);
+template hipError_t launch_minres_apply<float>(const mbl_basis_s*, const FieldArgs&,
+                                               const MinresState*, const float*, float*, double*,
+                                               hipStream_t);
+
+hipError_t launch_precond(const mbl_basis_s* b, const FieldArgs& F, int kind, const double* z,
+                          double* q, hipStream_t s) {
+  hipLaunchKernelGGL(k_precond, dim3(row_grid(b)), dim3(kWG), row_lds_bytes(b), s, b->dev(), F,
+                     kind, z, q);
+  return hipGetLastError();
+}
+
+hipError_t launch_residual(const mbl_basis_s* b, const FieldArgs& F, int precond,
+                           const double* rhs, const double* x, double* r, double* partials,
+                           int* nparts, hipStream_t s) {
+  const int g = row_grid(b);
+  if (nparts) *nparts = g;
+  hipLaunchKernelGGL(k_residual, dim3(g), dim3(kWG), row_lds_bytes(b), s, b->dev(), F, precond,
+                     rhs, x, r, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_states(const mbl_basis_s* b, uint32_t* states, hipStream_t s) {
+  hipLaunchKernelGGL(k_states, dim3(row_grid(b)), dim3(kWG), row_lds_bytes(b), s, b->dev(),
+                     states);
+  return hipGetLastError();
+}
+
+hipError_t launch_rank(const mbl_basis_s* b, const uint32_t* states, int64_t count,
+                       int64_t* ranks, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  const int64_t g = (count + kWG - 1) / kWG;
+  hipLaunchKernelGGL(k_rank, dim3((unsigned)g), dim3(kWG), 0, s, b->dev(), states, count, ranks);
+  return hipGetLastError();
+}
+
+hipError_t launch_twist(const mbl_basis_s* b, const double* psi, int64_t ld, int nvec,
+                        const double* costab, const double* sintab, double* partials, int* nparts,
+                        hipStream_t s) {
+  TwistTables T{};
+  for (int m = 0; m < 2 * b->L; ++m) {
+    T.c[m] = costab[m];
+    T.s[m] = sintab[m];
+  }
+  int g = row_grid(b);
+  if (g * nvec > kMaxPartials * 32) g = (kMaxPartials * 32) / nvec;
+  if (g < 1) g = 1;
+  if (nparts) *nparts = g;
+  hipLaunchKernelGGL(k_twist, dim3(g, nvec), dim3(kWG), row_lds_bytes(b), s, b->dev(), T, psi, ld,
+                     partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot(int64_t n, const double* x, const double* y, double* partials, int* nparts,
+                      hipStream_t s) {
+  const int g = dense_grid(n);
+  if (nparts) *nparts = g;
+  hipLaunchKernelGGL(k_dot, dim3(g), dim3(kWG), 0, s, n, x, y, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double* partials, int nparts, int stride, int nvals, double* out,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce, dim3(nvals), dim3(kWG), 0, s, partials, nparts, stride, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpby(int64_t n, double a, const double* x, double b, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpby, dim3(dense_grid(n)), dim3(kWG), 0, s, n, a, x, b, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale_copy(int64_t n, double a, const double* x, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_copy, dim3(dense_grid(n)), dim3(kWG), 0, s, n, a, x, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(int64_t n, double v, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill, dim3(dense_grid(n)), dim3(kWG), 0, s, n, v, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_splitmix(int64_t n, uint64_t seed, double* y, hipStream_t s) {
+  hipLaunchKernelGGL(k_splitmix, dim3(dense_grid(n)), dim3(kWG), 0, s, n, seed, y);
+  return hipGetLastError();
+}
+
+}  // namespace mbl

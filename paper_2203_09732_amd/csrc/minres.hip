@@ -1,0 +1,423 @@
+// Preconditioned MINRES for (H - sigma I) x = b (App. A, Alg. 2) on gfx950.
+//
+// One iteration k is three launches on the same stream:
+//   1. p = A q_k with fused partial sums of q_k . p            (row kernel)
+//   2. alpha_k = q.p / beta_k^2; z_{k+1} = p/beta_k - (alpha_k/beta_k) z_k
+//      - (beta_k/beta_{k-1}) z_{k-1}; q_{k+1} = M^{-1} z_{k+1} with M
+//      regenerated from the state bits; partial sums of q_{k+1} . z_{k+1}
+//                                                              (row kernel)
+//   3. beta_{k+1}, the Givens rotation, d_k and x_k += tau_k d_k
+//                                                              (flat kernel)
+// Every workgroup reduces the partial sums itself in the same fixed order,
+// so all workgroups hold bitwise identical scalars without a host round
+// trip. The scalar state lives in device memory in two slots (k & 1); once
+// |phi_k| < tol or k = kmax the state is marked done and later launches
+// return at once (the host checks the state one chunk of iterations behind).
+//
+// Vector slots: z_{k-1}/z_{k+1} share a buffer (updated in place), so do
+// d_{k-2}/d_k; q_k and q_{k+1} alternate. With p and x that is 8 n-vectors
+// besides b.
+#include "mbl_internal.h"
+
+#include <algorithm>
+#include <cmath>
+
+namespace mbl {
+
+__device__ __forceinline__ uint32_t uni_m(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ double wave_sum_m(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ double block_sum_m(double v, double* red) {
+  v = wave_sum_m(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < kWavesPerWG; ++w) s += red[w];
+  return s;
+}
+
+// every workgroup: identical fixed-order sum of P partials
+__device__ __forceinline__ double reduce_partials(const double* __restrict__ p, int P,
+                                                  double* red) {
+  double v = 0.0;
+  for (int i = threadIdx.x; i < P; i += blockDim.x) v += p[i];
+  return block_sum_m(v, red);
+}
+
+// ---- row machinery (same decomposition as the apply kernel) --------------
+struct MTables {
+  const double* lut;
+  double* red;
+  const uint16_t* state;
+};
+
+__device__ __forceinline__ MTables msetup(const DevBasis& B, const FieldArgs& F,
+                                          unsigned char* smem) {
+  double* lut = reinterpret_cast<double*>(smem);
+  double* red = lut + 128;
+  uint16_t* state = reinterpret_cast<uint16_t*>(red + 8);
+  const int nnib = (B.L + 3) >> 2;
+  for (int t = threadIdx.x; t < nnib * 16; t += blockDim.x) {
+    const int k = t >> 4, v = t & 15;
+    double acc = 0.0;
+    for (int b = 0; b < 4; ++b) {
+      const int site = 4 * k + b;
+      if (site < B.L && ((v >> b) & 1)) acc += F.h[site];
+    }
+    lut[t] = acc;
+  }
+  const int words = (1 << B.nlo) >> 1;
+  const uint32_t* gs = reinterpret_cast<const uint32_t*>(B.lo_state);
+  uint32_t* ss = reinterpret_cast<uint32_t*>(state);
+  for (int t = threadIdx.x; t < words; t += blockDim.x) ss[t] = gs[t];
+  return MTables{lut, red, state};
+}
+
+__device__ __forceinline__ double mprecond(const DevBasis& B, const FieldArgs& F,
+                                           const MTables& t, int kind, uint32_t a) {
+  if (kind == MBL_PRECOND_ID) return 1.0;
+  const uint32_t mask = (B.L == 32) ? 0xffffffffu : ((1u << B.L) - 1u);
+  const uint32_t rot = ((a << 1) | (a >> (B.L - 1))) & mask;
+  const int nanti = __popc(a ^ rot);
+  const int nnib = (B.L + 3) >> 2;
+  double f = 0.0;
+  for (int k = 0; k < nnib; ++k) f += t.lut[(k << 4) + ((a >> (4 * k)) & 15u)];
+  const double dsh = F.c0 - 0.5 * (double)nanti - f;
+  if (kind == MBL_PRECOND_ROW) return sqrt(dsh * dsh + 0.25 * (double)nanti);
+  return fabs(dsh);
+}
+
+template <typename Body>
+__device__ __forceinline__ void mfor_rows(const DevBasis& B, const MTables& t, Body body) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wave = uni_m(threadIdx.x >> 6);
+  const uint32_t stride = gridDim.x * kWavesPerWG;
+  for (uint32_t c = blockIdx.x * kWavesPerWG + wave; c < (uint32_t)B.nchunks; c += stride) {
+    const uint4 ch = B.chunks[c];
+    const uint32_t hi = uni_m(ch.x), j0 = uni_m(ch.y), cnt = uni_m(ch.z), row0 = uni_m(ch.w);
+    const uint32_t coff = uni_m(B.lo_coff[B.half - __popc(hi)]);
+    if (lane < cnt) {
+      const uint32_t lo = t.state[coff + j0 + lane];
+      body(row0 + lane, (hi << B.nlo) | lo);
+    }
+  }
+}
+
+// ---- initialisation: z_0 = 0, z_1 = scale * (src - Ax0), q_1 = M^{-1} z_1,
+// d_{-1} = d_0 = 0, e = 0 (if given); partial sums of q_1 . z_1.
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_minres_init(DevBasis B, FieldArgs F, int kind,
+                                                     const double* __restrict__ src,
+                                                     const T* __restrict__ ax0, double scale,
+                                                     T* z0, T* z1, T* q1, T* d0, T* d1, T* e,
+                                                     double* __restrict__ partials) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const MTables t = msetup(B, F, smem);
+  __syncthreads();
+  double acc = 0.0;
+  mfor_rows(B, t, [&](uint32_t row, uint32_t a) {
+    double zi = src[row];
+    if (ax0) zi -= (double)ax0[row];
+    const T zt = (T)(scale * zi);
+    const T qt = (T)((double)zt / mprecond(B, F, t, kind, a));
+    z0[row] = (T)0;
+    z1[row] = zt;
+    q1[row] = qt;
+    d0[row] = (T)0;
+    d1[row] = (T)0;
+    if (e) e[row] = (T)0;
+    acc += (double)qt * (double)zt;
+  });
+  const double s = block_sum_m(acc, t.red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+__global__ void k_minres_init_state(const double* __restrict__ partials, int P, double tol,
+                                    int64_t kmax, MinresState* S) {
+  __shared__ double red[kWavesPerWG];
+  const double qz = reduce_partials(partials, P, red);
+  if (threadIdx.x == 0) {
+    const double beta = sqrt(qz);
+    MinresState s0;
+    s0.beta_prev = 1.0;
+    s0.beta = beta;
+    s0.c = 1.0;
+    s0.s = 0.0;
+    s0.dhat = 0.0;
+    s0.eps = 0.0;
+    s0.phi = beta;
+    s0.k = 0;
+    s0.bad = !isfinite(beta);
+    s0.done = !(fabs(beta) >= tol && 0 < kmax);
+    S[0] = s0;
+  }
+}
+
+// ---- step 1: p = A q_k, partial sums of q_k . p: the apply kernel of
+// kernels.hip guarded by the done flag (launch_minres_apply).
+
+// ---- step 2: z_{k+1}, q_{k+1}, partial sums of q_{k+1} . z_{k+1} -------------
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_minres_zq(DevBasis B, FieldArgs F, int kind,
+                                                   const MinresState* __restrict__ Sin,
+                                                   const double* __restrict__ part1, int P1,
+                                                   const T* __restrict__ p, const T* __restrict__ zk,
+                                                   T* __restrict__ zkm1, T* __restrict__ qnext,
+                                                   double* __restrict__ part2) {
+  if (Sin->done) return;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const MTables t = msetup(B, F, smem);
+  const double qp = reduce_partials(part1, P1, t.red);
+  const double beta = Sin->beta, beta_prev = Sin->beta_prev;
+  const double alpha = qp / (beta * beta);
+  const double c1 = 1.0 / beta, c2 = alpha / beta, c3 = beta / beta_prev;
+  double acc = 0.0;
+  mfor_rows(B, t, [&](uint32_t row, uint32_t a) {
+    const double zn = c1 * (double)p[row] - c2 * (double)zk[row] - c3 * (double)zkm1[row];
+    const T zt = (T)zn;
+    const T qt = (T)((double)zt / mprecond(B, F, t, kind, a));
+    zkm1[row] = zt;
+    qnext[row] = qt;
+    acc += (double)qt * (double)zt;
+  });
+  const double s = block_sum_m(acc, t.red);
+  if (threadIdx.x == 0) part2[blockIdx.x] = s;
+}
+
+// ---- step 3: Givens rotation, d_k, x_k (flat kernel) -----------------------
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_minres_dx(int64_t n, const MinresState* __restrict__ Sin,
+                                                   MinresState* __restrict__ Sout,
+                                                   const double* __restrict__ part1, int P1,
+                                                   const double* __restrict__ part2, int P2,
+                                                   double tol, int64_t kmax,
+                                                   const T* __restrict__ qk, const T* __restrict__ dkm1,
+                                                   T* __restrict__ dkm2, T* __restrict__ x) {
+  __shared__ double red[kWavesPerWG];
+  const MinresState si = *Sin;
+  if (si.done) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *Sout = si;   // carry the final state forward
+    return;
+  }
+  const double qp = reduce_partials(part1, P1, red);
+  const double qz = reduce_partials(part2, P2, red);
+  const double beta = si.beta;
+  const double alpha = qp / (beta * beta);
+  const double beta_next = sqrt(qz);
+  const double delta = si.c * si.dhat + si.s * alpha;
+  const double gamma_hat = -si.s * si.dhat + si.c * alpha;
+  const double eps_next = si.s * beta_next;
+  const double dhat_next = si.c * beta_next;
+  const double gamma = sqrt(gamma_hat * gamma_hat + beta_next * beta_next);
+  const double c = gamma_hat / gamma;
+  const double s = beta_next / gamma;
+  const double tau = c * si.phi;
+  const double phi = -s * si.phi;
+  const double inv_beta = 1.0 / beta, inv_gamma = 1.0 / gamma;
+  const double eps = si.eps;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double d = ((double)qk[i] * inv_beta - delta * (double)dkm1[i] - eps * (double)dkm2[i]) *
+                     inv_gamma;
+    const T dt = (T)d;
+    dkm2[i] = dt;
+    x[i] = (T)((double)x[i] + tau * (double)dt);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    MinresState so;
+    so.beta_prev = beta;
+    so.beta = beta_next;
+    so.c = c;
+    so.s = s;
+    so.dhat = dhat_next;
+    so.eps = eps_next;
+    so.phi = phi;
+    so.k = si.k + 1;
+    so.bad = !isfinite(phi) || !isfinite(alpha) || !isfinite(beta_next);
+    so.done = so.bad || !(fabs(phi) >= tol && so.k < kmax);
+    *Sout = so;
+  }
+}
+
+// x64 += scale * e
+__global__ __launch_bounds__(kWG) void k_add_scaled_f32(int64_t n, double scale,
+                                                        const float* __restrict__ e,
+                                                        double* __restrict__ x) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] += scale * (double)e[i];
+}
+
+
+static int flat_grid(int64_t n) {
+  int64_t g = (n + kWG - 1) / kWG;
+  if (g > 2048) g = 2048;
+  return (int)(g < 1 ? 1 : g);
+}
+
+static size_t mlds(const mbl_basis_s* b) {
+  return (128 + 8) * sizeof(double) + sizeof(uint16_t) * ((size_t)1 << b->nlo);
+}
+
+// Runs Alg. 2 on vectors of type T. src: FP64 right-hand side (scaled by
+// scale on entry). x: T solution (x0 on entry unless x0_zero).
+template <typename T>
+static mbl_status minres_core(mbl_basis_s* b, const FieldArgs& F, const double* src,
+                              double scale, T* x, bool x0_zero, double tol, int64_t kmax,
+                              int precond, mbl_workspace_s* ws, int64_t* iters, double* phi,
+                              hipStream_t s) {
+  const int64_t n = b->n;
+  T* Z[2] = {(T*)ws->z[0], (T*)ws->z[1]};
+  T* Q[2] = {(T*)ws->q[0], (T*)ws->q[1]};
+  T* D[2] = {(T*)ws->d[0], (T*)ws->d[1]};
+  T* P = (T*)ws->p;
+  const int G = row_grid(b);
+  const size_t lds = mlds(b);
+  const DevBasis B = b->dev();
+  MinresState* S = ws->state;
+
+  // p = A x0 (skipped when x0 = 0)
+  if (!x0_zero) MBL_HIP(launch_apply<T>(b, F, x, P, 0, nullptr, nullptr, s));
+  // z_0 = 0 in Z[0], z_1 in Z[1], q_1 in Q[1], d_{-1} in D[1], d_0 in D[0]
+  hipLaunchKernelGGL((k_minres_init<T>), dim3(G), dim3(kWG), lds, s, B, F, precond, src,
+                     x0_zero ? (const T*)nullptr : (const T*)P, scale, Z[0], Z[1], Q[1], D[0],
+                     D[1], x0_zero ? x : (T*)nullptr, ws->partials2);
+  MBL_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_minres_init_state, dim3(1), dim3(kWG), 0, s, ws->partials2, G, tol, kmax,
+                     S);
+  MBL_HIP(hipGetLastError());
+
+  const int64_t kChunkIters = 64;
+  int64_t issued = 0;
+  int pending = 0;       // status copies in flight (0..2)
+  int slot = 0;
+  bool done = false;
+  MinresState last{};
+  const int FG = flat_grid(n);
+  // a state copy for the chunk ending at iteration k goes to h_state[slot]
+  auto check = [&](int which) -> mbl_status {
+    MBL_HIP(hipEventSynchronize(ws->ev[which]));
+    last = ws->h_state[which];
+    if (last.done) done = true;
+    return MBL_OK;
+  };
+  while (!done && issued < kmax) {
+    const int64_t k_end = std::min(kmax, issued + kChunkIters);
+    for (int64_t k = issued + 1; k <= k_end; ++k) {
+      const MinresState* Sin = S + ((k - 1) & 1);
+      MinresState* Sout = S + (k & 1);
+      T* qk = Q[k & 1];
+      T* qn = Q[(k + 1) & 1];
+      T* zk = Z[k & 1];
+      T* zkm1 = Z[(k + 1) & 1];
+      T* dkm1 = D[(k - 1) & 1];
+      T* dkm2 = D[k & 1];
+      MBL_HIP(launch_minres_apply<T>(b, F, Sin, qk, P, ws->partials1, s));
+      hipLaunchKernelGGL((k_minres_zq<T>), dim3(G), dim3(kWG), lds, s, B, F, precond, Sin,
+                         ws->partials1, G, P, zk, zkm1, qn, ws->partials2);
+      hipLaunchKernelGGL((k_minres_dx<T>), dim3(FG), dim3(kWG), 0, s, n, Sin, Sout,
+                         ws->partials1, G, ws->partials2, G, tol, kmax, qk, dkm1, dkm2, x);
+    }
+    MBL_HIP(hipGetLastError());
+    issued = k_end;
+    MBL_HIP(hipMemcpyAsync(&ws->h_state[slot], S + (issued & 1), sizeof(MinresState),
+                           hipMemcpyDeviceToHost, s));
+    MBL_HIP(hipEventRecord(ws->ev[slot], s));
+    ++pending;
+    if (pending == 2) {     // wait for the previous chunk's status, keep one chunk queued
+      MBL_TRY(check(slot ^ 1));
+      --pending;
+    }
+    slot ^= 1;
+  }
+  // drain: the most recent status copy is in slot ^ 1
+  if (pending > 0) MBL_TRY(check(slot ^ 1));
+  if (!done) {  // issued == kmax without a done flag in the copies (cannot happen) : sync once
+    MBL_HIP(hipMemcpyAsync(&ws->h_state[0], S + (issued & 1), sizeof(MinresState),
+                           hipMemcpyDeviceToHost, s));
+    MBL_HIP(hipStreamSynchronize(s));
+    last = ws->h_state[0];
+  }
+  *iters = last.k;
+  *phi = last.phi;
+  if (last.bad) {
+    set_error("MINRES met a non-finite value (singular preconditioner or breakdown)");
+    return MBL_ERR_NUMERIC;
+  }
+  return (fabs(last.phi) < tol) ? MBL_OK : MBL_WARN_NOCONV;
+}
+
+mbl_status minres_run(mbl_basis_s* b, const double* h_host, double sigma, const double* rhs,
+                      double* x, double tol, int64_t kmax, int precision, int precond,
+                      bool x0_zero, mbl_workspace_s* ws, mbl_minres_info* info, hipStream_t s) {
+  const FieldArgs F = make_fields(b, h_host, sigma);
+  const int64_t n = b->n;
+  mbl_minres_info inf{};
+  mbl_status st = MBL_OK;
+  if (precision == MBL_FP64) {
+    int64_t it = 0;
+    double phi = 0;
+    st = minres_core<double>(b, F, rhs, 1.0, x, x0_zero, tol, kmax, precond, ws, &it, &phi, s);
+    if (st < 0) return st;
+    inf.iters = it;
+    inf.phi = phi;
+  } else {
+    // FP32 inner solves, FP64 residual recomputation and restart.
+    // Each cycle solves A e = r / ||r||_{M^-1} in FP32 to a relative
+    // tolerance eta and updates x += ||r||_{M^-1} e in FP64.
+    const double eta = 1e-6;
+    const int max_restarts = 200;
+    int64_t total = 0;
+    int restarts = 0;
+    double rM = 0.0;
+    bool first = true;
+    for (;;) {
+      int np = 0;
+      if (first && x0_zero) MBL_HIP(launch_fill(n, 0.0, x, s));
+      MBL_HIP(launch_residual(b, F, precond, rhs, x, ws->r64, ws->partials1, &np, s));
+      double sums[2];
+      MBL_TRY(reduce_to_host(ws, ws->partials1, np, 2, 2, sums, s));
+      rM = std::sqrt(sums[0]);
+      first = false;
+      if (!(rM >= tol) || total >= kmax || restarts >= max_restarts) break;
+      const double inner_tol = std::max(eta, 0.5 * tol / rM);
+      int64_t it = 0;
+      double phi = 0;
+      mbl_status s2 = minres_core<float>(b, F, ws->r64, 1.0 / rM, (float*)ws->e, true, inner_tol,
+                                         kmax - total, precond, ws, &it, &phi, s);
+      if (s2 < 0) return s2;
+      total += it;
+      hipLaunchKernelGGL(k_add_scaled_f32, dim3(flat_grid(n)), dim3(kWG), 0, s, n, rM,
+                         (const float*)ws->e, x);
+      MBL_HIP(hipGetLastError());
+      ++restarts;
+    }
+    inf.iters = total;
+    inf.restarts = restarts;
+    inf.phi = rM;
+    st = (rM < tol) ? MBL_OK : MBL_WARN_NOCONV;
+    if (!std::isfinite(rM)) {
+      set_error("non-finite residual in FP32-inner MINRES");
+      return MBL_ERR_NUMERIC;
+    }
+  }
+  // true residual ||b - (H - sigma) x||_2 in FP64
+  {
+    int np = 0;
+    MBL_HIP(launch_residual(b, F, precond, rhs, x, ws->r64, ws->partials1, &np, s));
+    double sums[2];
+    MBL_TRY(reduce_to_host(ws, ws->partials1, np, 2, 2, sums, s));
+    inf.true_res = std::sqrt(sums[1]);
+  }
+  if (info) *info = inf;
+  return st;
+}
+
+}  // namespace mbl

@@ -1,0 +1,324 @@
+"""Parity of the HIP path against the CPU oracle, through the C ABI.
+
+Tolerances (derived in DESIGN.md, "Parity bar"):
+* indexing (states, ranks): bit-exact;
+* apply_H / preconditioner in FP64: |y - y_ref| <= 1e-13 max|y_ref| (the two
+  sides sum the diagonal in different orders);
+* apply_H in FP32 storage: <= 2e-6 max|y_ref| against the oracle applied to
+  the same FP32-rounded input;
+* MINRES: ||x - x_dense|| / ||x_dense|| <= 1e-8 at |phi| < 1e-12;
+* eigenpairs: |E - E_ref| / max(|E_ref|, 1) <= 1e-10, 1 - |<psi, psi_ref>|
+  <= 1e-10, twist |z - z_ref| <= 2 ||psi - psi_ref|| + 1e-12.
+"""
+import json
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import lanczos, minres, model, precond, twist
+from workloads import disorder_fields, gaussian_vector, start_vector
+
+pytestmark = pytest.mark.gpu
+HERE = os.path.dirname(os.path.abspath(__file__))
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+def dev(torch, a, dtype=None):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype or torch.float64, device="cuda")
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def oracle_rows(L, h, sigma, x, rows, states):
+    """(H - sigma) x at the given rows only, from the definitions in
+    oracle.model (diagonal and one swap per antiparallel bond)."""
+    st = states[rows]
+    y = (model.diagonal(L, h, st) - sigma) * x[rows]
+    for (a, b) in model.bonds(L):
+        anti = ((st >> (a - 1)) & 1) != ((st >> (b - 1)) & 1)
+        fl = st ^ ((1 << (a - 1)) | (1 << (b - 1)))
+        idx = np.clip(np.searchsorted(states, fl), 0, len(states) - 1)
+        assert np.array_equal(states[idx][anti], fl[anti])
+        y = y + np.where(anti, 0.5 * x[idx], 0.0)
+    return y
+
+
+# ---------------------------------------------------------------- basis
+@pytest.mark.parametrize("L,lo", [(4, 0), (4, 1), (4, 3), (6, 0), (8, 0), (8, 2), (10, 0),
+                                  (12, 5), (14, 0), (16, 0), (16, 9), (18, 0), (20, 0), (22, 0)])
+def test_states_bit_exact(gpu, torch, L, lo):
+    say(f"states L={L} lo_bits={lo}")
+    b = gpu.Basis(L, lo)
+    ref = model.sector_states(L)
+    assert b.n == len(ref) == math.comb(L, L // 2)
+    got = host(b.states())
+    assert np.array_equal(got, ref)
+
+
+@pytest.mark.parametrize("L", [8, 14, 20])
+def test_rank_round_trip_and_out_of_sector(gpu, torch, L):
+    say(f"rank L={L}")
+    b = gpu.Basis(L)
+    ref = model.sector_states(L)
+    rng = np.random.default_rng(L)
+    idx = rng.choice(len(ref), size=min(5000, len(ref)), replace=False)
+    r = host(b.rank(dev(torch, ref[idx], torch.int64)))
+    assert np.array_equal(r, idx)
+    bad = np.array([0, (1 << L) - 1, 1, (1 << L) | 3, 0b111], dtype=np.int64)
+    assert np.all(host(b.rank(dev(torch, bad, torch.int64))) == -1)
+
+
+# ---------------------------------------------------------------- apply_H
+@pytest.mark.parametrize("L,lo,seed", [(4, 0, 0), (4, 1, 1), (6, 0, 2), (8, 3, 3), (10, 0, 4),
+                                       (12, 0, 5), (12, 7, 6), (14, 0, 0), (16, 0, 7),
+                                       (16, 6, 8)])
+def test_apply_dense_parity(gpu, torch, L, lo, seed):
+    say(f"apply L={L} lo_bits={lo} seed={seed}")
+    h = disorder_fields(L, 3.0, seed)
+    sigma = 0.3 * (seed - 3)
+    b = gpu.Basis(L, lo)
+    x = gaussian_vector(b.n, seed + 100)
+    H = model.hamiltonian_csr(L, h)
+    yref = H @ x - sigma * x
+    y = host(gpu.apply_H(b, h, sigma, dev(torch, x)))
+    assert np.abs(y - yref).max() <= 1e-13 * np.abs(yref).max()
+
+
+@pytest.mark.parametrize("L", [10, 14])
+def test_apply_f32_parity(gpu, torch, L):
+    say(f"apply f32 L={L}")
+    h = disorder_fields(L, 3.0, 1)
+    b = gpu.Basis(L)
+    x32 = gaussian_vector(b.n, 5).astype(np.float32)
+    yref = model.hamiltonian_csr(L, h) @ x32.astype(np.float64) - 0.25 * x32
+    y = host(gpu.apply_H(b, h, 0.25, dev(torch, x32, torch.float32))).astype(np.float64)
+    assert np.abs(y - yref).max() <= 2e-6 * np.abs(yref).max()
+
+
+@pytest.mark.parametrize("L,samples", [(20, 4000), (22, 4000), (24, 3000)])
+def test_apply_sampled_rows_large(gpu, torch, L, samples):
+    """Full-size launch, rows checked one by one by the oracle."""
+    say(f"apply sampled L={L}")
+    h = disorder_fields(L, 3.5, 11)
+    b = gpu.Basis(L)
+    states = model.sector_states(L)
+    x = gaussian_vector(b.n, 12)
+    y = host(gpu.apply_H(b, h, -0.4, dev(torch, x)))
+    rng = np.random.default_rng(L)
+    rows = np.unique(np.concatenate([rng.integers(0, b.n, samples), [0, 1, b.n - 2, b.n - 1]]))
+    yref = oracle_rows(L, h, -0.4, x, rows, states)
+    assert np.abs(y[rows] - yref).max() <= 1e-13 * np.abs(yref).max()
+
+
+def test_apply_symmetric_and_deterministic(gpu, torch):
+    say("apply symmetry/determinism L=18")
+    L = 18
+    h = disorder_fields(L, 2.0, 3)
+    b = gpu.Basis(L)
+    u = dev(torch, gaussian_vector(b.n, 1))
+    v = dev(torch, gaussian_vector(b.n, 2))
+    Hu = gpu.apply_H(b, h, 0.0, u)
+    Hv = gpu.apply_H(b, h, 0.0, v)
+    a1 = gpu.dot(v, Hu)
+    a2 = gpu.dot(u, Hv)
+    assert abs(a1 - a2) <= 1e-12 * abs(a1)
+    Hu2 = gpu.apply_H(b, h, 0.0, u)
+    assert torch.equal(Hu, Hu2)
+
+
+# ---------------------------------------------------------------- precond
+@pytest.mark.parametrize("kind", ["row", "jacobi", "id"])
+def test_precond_parity(gpu, torch, kind):
+    say(f"precond {kind}")
+    L = 12
+    h = disorder_fields(L, 3.0, 2)
+    b = gpu.Basis(L)
+    z = gaussian_vector(b.n, 3)
+    H = model.hamiltonian_csr(L, h)
+    m = precond.preconditioner_diagonal(H, 0.123, kind)
+    q = host(gpu.precond_apply(b, h, 0.123, dev(torch, z), kind=kind))
+    assert np.abs(q - z / m).max() <= 1e-13 * np.abs(z / m).max()
+
+
+# ---------------------------------------------------------------- MINRES
+def _problem(L, h, seed):
+    f = disorder_fields(L, h, seed)
+    H = model.hamiltonian_csr(L, f)
+    w = np.linalg.eigvalsh(H.toarray())
+    return f, H, 0.5 * (w[0] + w[-1])
+
+
+@pytest.mark.parametrize("L,h,seed,kind", [(10, 3.0, 0, "row"), (12, 2.0, 1, "row"),
+                                           (14, 3.0, 0, "row"), (10, 3.0, 2, "jacobi"),
+                                           (10, 3.0, 3, "id")])
+def test_minres_parity(gpu, torch, L, h, seed, kind):
+    say(f"minres L={L} h={h} seed={seed} {kind}")
+    f, H, sigma = _problem(L, h, seed)
+    bvec = gaussian_vector(H.shape[0], 7)
+    bvec /= np.linalg.norm(bvec)
+    b = gpu.Basis(L)
+    x, info = gpu.minres_solve(b, f, sigma, dev(torch, bvec), tol=1e-12, precond=kind)
+    assert info.status == 0
+    xd = minres.solve_dense(H.toarray(), sigma, bvec)
+    assert np.linalg.norm(host(x) - xd) / np.linalg.norm(xd) <= 1e-8
+    assert info.phi < 1e-12
+    if L <= 12:
+        A = precond.shifted(H, sigma)
+        m = precond.preconditioner_diagonal(H, sigma, kind)
+        _, k_ref, _ = minres.minres(lambda v: A @ v, np.zeros_like(bvec), bvec, 1.0 / m,
+                                    10**6, 1e-12)
+        assert abs(info.iters - k_ref) <= 0.01 * k_ref + 3
+
+
+def test_minres_nonzero_start_and_kmax_warning(gpu, torch):
+    say("minres x0 / kmax")
+    L = 10
+    f, H, sigma = _problem(L, 3.0, 4)
+    bvec = gaussian_vector(H.shape[0], 8)
+    b = gpu.Basis(L)
+    xd = minres.solve_dense(H.toarray(), sigma, bvec)
+    x0 = dev(torch, xd + 1e-3 * gaussian_vector(H.shape[0], 9))
+    x, info = gpu.minres_solve(b, f, sigma, dev(torch, bvec), x=x0, tol=1e-12)
+    assert info.status == 0
+    assert np.linalg.norm(host(x) - xd) / np.linalg.norm(xd) <= 1e-8
+    x, info = gpu.minres_solve(b, f, sigma, dev(torch, bvec), tol=1e-12, kmax=5)
+    assert info.status == gpu.WARN_NOCONV and info.iters == 5
+
+
+@pytest.mark.parametrize("L,seed", [(12, 0), (14, 1)])
+def test_minres_fp32_inner_parity(gpu, torch, L, seed):
+    say(f"minres fp32-inner L={L}")
+    f, H, sigma = _problem(L, 3.0, seed)
+    bvec = gaussian_vector(H.shape[0], 7)
+    bvec /= np.linalg.norm(bvec)
+    b = gpu.Basis(L)
+    x, info = gpu.minres_solve(b, f, sigma, dev(torch, bvec), tol=1e-12, precision="fp32_inner")
+    assert info.status == 0 and info.restarts >= 1
+    xd = minres.solve_dense(H.toarray(), sigma, bvec)
+    assert np.linalg.norm(host(x) - xd) / np.linalg.norm(xd) <= 1e-8
+
+
+def test_minres_deterministic(gpu, torch):
+    say("minres determinism")
+    L = 12
+    f, H, sigma = _problem(L, 3.0, 5)
+    b = gpu.Basis(L)
+    bv = dev(torch, gaussian_vector(H.shape[0], 1))
+    x1, i1 = gpu.minres_solve(b, f, sigma, bv, tol=1e-10)
+    x2, i2 = gpu.minres_solve(b, f, sigma, bv, tol=1e-10)
+    assert i1.iters == i2.iters and torch.equal(x1, x2)
+
+
+# ---------------------------------------------------------------- sigma, twist, residuals
+@pytest.mark.parametrize("L,seed", [(12, 0), (14, 0), (16, 2)])
+def test_sigma_midpoint(gpu, torch, L, seed):
+    say(f"sigma L={L}")
+    f = disorder_fields(L, 3.0, seed)
+    H = model.hamiltonian_csr(L, f)
+    lo, hi = lanczos.extremal_eigenvalues(H)
+    b = gpu.Basis(L)
+    emin, emax, sg = gpu.sigma_midpoint(b, f, 1e-10)
+    assert abs(emin - lo) <= 1e-10 * abs(lo) and abs(emax - hi) <= 1e-10 * abs(hi)
+    assert abs(sg - 0.5 * (lo + hi)) <= 1e-10 * max(abs(lo), abs(hi))
+
+
+@pytest.mark.parametrize("L", [4, 8, 12, 16, 20])
+def test_twist_parity(gpu, torch, L):
+    say(f"twist L={L}")
+    b = gpu.Basis(L)
+    rng = np.random.default_rng(L)
+    P = rng.standard_normal((b.n, 3))
+    P /= np.linalg.norm(P, axis=0)
+    z = gpu.twist_expect(b, dev(torch, P))
+    zr = twist.twist_overlap(L, P)
+    assert np.abs(z - zr).max() <= 1e-13
+    # the uniform superposition has z = 0 (lemma of App. B)
+    u = np.full(b.n, 1 / math.sqrt(b.n))
+    assert abs(gpu.twist_expect(b, dev(torch, u))[0]) <= 1e-13
+
+
+def test_eig_residual_parity(gpu, torch):
+    say("eig residual")
+    L = 10
+    f = disorder_fields(L, 3.0, 1)
+    H = model.hamiltonian_dense(L, f)
+    w, V = np.linalg.eigh(H)
+    b = gpu.Basis(L)
+    P = V[:, 100:104] + 1e-6 * np.random.default_rng(0).standard_normal((b.n, 4))
+    E = w[100:104]
+    r = gpu.eig_residual(b, f, E, dev(torch, P))
+    rr = lanczos.eigen_residuals(H, E, P)
+    assert np.allclose(r, rr, rtol=1e-10, atol=1e-15)
+
+
+# ---------------------------------------------------------------- shift-invert Lanczos
+def test_si_lanczos_plain_L14(gpu, torch):
+    """The L=14 plain workload: 10 pairs nearest the midpoint, FP64."""
+    g = json.load(open(os.path.join(HERE, "golden", "plain_L14_h3_seed0.json")))
+    L, f, sigma, nev = g["L"], np.array(g["fields"]), g["sigma"], g["nev"]
+    say(f"si_lanczos L={L} nev={nev}")
+    b = gpu.Basis(L)
+    v0 = dev(torch, start_vector(b.n, 0))
+    escale = max(abs(g["E_min"]), abs(g["E_max"]))
+    res = gpu.si_lanczos(b, f, sigma, nev, minres_tol=1e-12, eig_tol=1e-10, escale=escale,
+                         v0=v0)
+    say(f"  steps={res.steps} minres_iters={res.minres_iters} nconv={res.nconv} "
+        f"max_rel={res.max_rel_resid:.2e} t={res.seconds:.2f}s")
+    assert res.status == 0 and res.nconv == nev
+    Eref = np.array(g["evals"])
+    assert np.all(np.abs(res.evals - Eref) / np.maximum(np.abs(Eref), 1) <= 1e-10)
+    H = model.hamiltonian_dense(L, f)
+    _, Vref = lanczos.eigenpairs_dense(H, sigma, nev)
+    U = host(res.evecs)
+    ov = np.abs(np.sum(U * Vref, axis=0))
+    assert np.all(1 - ov <= 1e-10), 1 - ov
+    # explicit residuals agree with the oracle's
+    rr = lanczos.eigen_residuals(H, res.evals, U)
+    assert np.all(rr <= 1e-10 * escale)
+    assert np.allclose(res.resid, rr, rtol=1e-6, atol=1e-14)
+    z = gpu.twist_expect(b, res.evecs)
+    zref = np.array(g["z_re"]) + 1j * np.array(g["z_im"])
+    # ||psi - psi_ref|| with the sign aligned (the overlap itself rounds to 1)
+    dpsi = np.minimum(np.linalg.norm(U - Vref, axis=0), np.linalg.norm(U + Vref, axis=0))
+    assert np.all(np.abs(z - zref) <= 2 * dpsi + 1e-12)
+    assert np.all(np.abs(z) <= 1 + 1e-12)
+
+
+def test_si_lanczos_fp32_inner_L12(gpu, torch):
+    say("si_lanczos fp32-inner L=12")
+    L, nev = 12, 6
+    f, H, sigma = _problem(L, 3.0, 2)
+    b = gpu.Basis(L)
+    res = gpu.si_lanczos(b, f, sigma, nev, precision="fp32_inner", v0=dev(torch, start_vector(b.n, 1)))
+    assert res.status == 0 and res.nconv == nev
+    Eref, Vref = lanczos.eigenpairs_dense(H.toarray(), sigma, nev)
+    assert np.all(np.abs(res.evals - Eref) / np.maximum(np.abs(Eref), 1) <= 1e-10)
+    ov = np.abs(np.sum(host(res.evecs) * Vref, axis=0))
+    assert np.all(1 - ov <= 1e-10)
+
+
+def test_si_lanczos_seeded_start(gpu, torch):
+    say("si_lanczos seeded start L=10")
+    L, nev = 10, 4
+    f, H, sigma = _problem(L, 2.0, 7)
+    b = gpu.Basis(L)
+    res = gpu.si_lanczos(b, f, sigma, nev, seed=1234)
+    Eref, _ = lanczos.eigenpairs_dense(H.toarray(), sigma, nev)
+    assert res.nconv == nev
+    assert np.all(np.abs(res.evals - Eref) / np.maximum(np.abs(Eref), 1) <= 1e-10)
