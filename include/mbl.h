@@ -23,6 +23,10 @@
  *  - stream is a hipStream_t passed as void* (NULL = the null stream).
  *    Calls that return host values synchronize that stream; the others are
  *    asynchronous with respect to the host.
+ *  - The library calls the HIP runtime loaded in the process. A caller that
+ *    passes streams or device pointers from a framework must make sure one
+ *    HIP runtime is loaded (a framework bundling its own libamdhip64.so.7 is
+ *    loaded first, so this library binds to it).
  *  - Handles (mbl_basis, mbl_workspace) are created and freed by the library.
  *    A basis is immutable after creation and may be shared by streams; a
  *    workspace must not be used by two calls at once.
@@ -178,6 +182,56 @@ mbl_status mbl_eig_residual(mbl_basis b, const double* h_host, const double* E_h
  * mmax bounds the steps (0 = default 300). Synchronizes stream. */
 mbl_status mbl_sigma_midpoint(mbl_basis b, const double* h_host, double rel_tol, int mmax,
                               double* emin, double* emax, double* sigma, void* stream);
+
+/* ---- batched form: R realizations of one L in lockstep ---------------------
+ * R disorder realizations of the basis's chain length, each with its own
+ * fields h_r (h_host: R x L doubles, row r = realization r) and shift
+ * sigma_r (sigma_host: R doubles). Batched n-vectors are interleaved:
+ * element (i, r) at index i * R + r of an n * R array. R is a power of two,
+ * 2 <= R <= 32, and R * 16 * ceil(L/4) doubles of field tables must fit the
+ * kernels' 64 KB LDS budget (R = 32 up to L = 24, R = 16 at L = 26);
+ * otherwise MBL_ERR_ARG. The basis must use the default lo_bits, and L must
+ * be one of 12, 14, ..., 32. The batch workspace holds the recurrence vectors
+ * of all realizations and up to mmax Lanczos blocks (n * R * (mmax + 1)
+ * doubles). */
+typedef struct mbl_batch_s* mbl_batch;
+mbl_status mbl_batch_create(mbl_basis b, int R, int mmax, int nevmax, mbl_batch* out);
+void mbl_batch_free(mbl_batch w);
+mbl_status mbl_batch_bytes(mbl_batch w, int64_t* bytes);
+/* y_r = (H_r - sigma_r) x_r for every r (Eq. (1)); interleaved x, y. Async. */
+mbl_status mbl_apply_H_batched(mbl_basis b, mbl_batch w, const double* h_host,
+                               const double* sigma_host, const double* x_dev, double* y_dev,
+                               void* stream);
+mbl_status mbl_apply_H_batched_f32(mbl_basis b, mbl_batch w, const double* h_host,
+                                   const double* sigma_host, const float* x_dev, float* y_dev,
+                                   void* stream);
+/* Alg. 2 for every realization from x0 = 0 (x_dev is overwritten); per
+ * realization stop at |phi_r| < tol or kmax. iters_host[R], phi_host[R] may
+ * be NULL. MBL_WARN_NOCONV if any realization missed tol. Synchronizes. */
+mbl_status mbl_minres_solve_batched(mbl_basis b, mbl_batch w, const double* h_host,
+                                    const double* sigma_host, const double* rhs_dev,
+                                    double* x_dev, double tol, int64_t kmax, int precision,
+                                    int precond, int64_t* iters_host, double* phi_host,
+                                    void* stream);
+/* Alg. 1 for every realization in lockstep with the stopping rule of
+ * mbl_si_lanczos applied per realization (escale_host: R values or NULL); a
+ * realization that has converged stops taking steps (its MINRES right-hand
+ * side is zeroed). Outputs: evals_host[R * nev] (realization-major,
+ * ascending per realization), evecs_dev: nev interleaved blocks of n * R
+ * doubles (block t holds pair t of every realization), resid_host[R * nev]
+ * explicit FP64 residuals, info_host[R] (info_host[0].minres_iters holds the
+ * batch total). Synchronizes. */
+mbl_status mbl_si_lanczos_batched(mbl_basis b, mbl_batch w, const double* h_host,
+                                  const double* sigma_host, int nev, int mmax, double minres_tol,
+                                  int64_t minres_kmax, double eig_tol, double gap_tol,
+                                  const double* escale_host, const double* v0_dev, uint64_t seed,
+                                  int precision, int precond, double* evals_host,
+                                  double* evecs_dev, double* resid_host, mbl_si_info* info_host,
+                                  void* stream);
+/* z for nvec interleaved blocks (layout of mbl_si_lanczos_batched's evecs):
+ * z_host[((r * nvec) + t) * 2 + {0: Re, 1: Im}]. Synchronizes. */
+mbl_status mbl_twist_expect_batched(mbl_basis b, mbl_batch w, const double* psi_dev, int nvec,
+                                    double* z_host, void* stream);
 
 /* ---- small device helpers used by the bindings and tests ---------------- */
 /* out_host = sum_i x_i * y_i over n doubles, reduced in a fixed order. */

@@ -23,6 +23,14 @@ if not os.path.exists(LIB_PATH):
         f"{LIB_PATH} is missing: build it with `python -m paper_2203_09732_amd.build` "
         "(hipcc, gfx950). There is no fallback implementation.")
 
+# One HIP runtime per process: torch ships its own libamdhip64 (same SONAME,
+# libamdhip64.so.7, but NEEDED by torch under the bare name). Loading torch
+# first makes the dynamic loader resolve libmbl's dependency to the runtime
+# torch already mapped, so torch's streams and allocations and this library's
+# launches go through one runtime. Loading libmbl first would map a second
+# runtime beside torch's.
+import torch as _torch  # noqa: E402,F401
+
 lib = C.CDLL(LIB_PATH)
 
 OK, ERR_ARG, ERR_NOMEM, ERR_HIP, ERR_NUMERIC = 0, -1, -2, -3, -4
@@ -339,3 +347,146 @@ def tridiag_eig(alpha, beta):
     _check(lib.mbl_tridiag_eig(k, ap, bp, w.ctypes.data_as(_dp), V.ctypes.data_as(_dp)),
            "mbl_tridiag_eig", warn_ok=False)
     return w, V.reshape(k, k).T
+
+
+# ---------------------------------------------------------------- batched form
+_sig("mbl_batch_create", _i32, [_vp, C.c_int, C.c_int, C.c_int, C.POINTER(_vp)])
+_sig("mbl_batch_free", None, [_vp])
+_sig("mbl_batch_bytes", _i32, [_vp, C.POINTER(C.c_int64)])
+_sig("mbl_apply_H_batched", _i32, [_vp, _vp, _dp, _dp, _vp, _vp, _vp])
+_sig("mbl_apply_H_batched_f32", _i32, [_vp, _vp, _dp, _dp, _vp, _vp, _vp])
+_sig("mbl_minres_solve_batched", _i32, [_vp, _vp, _dp, _dp, _vp, _vp, _d, _i64, C.c_int, C.c_int,
+                                        C.POINTER(C.c_int64), _dp, _vp])
+_sig("mbl_si_lanczos_batched", _i32, [_vp, _vp, _dp, _dp, C.c_int, C.c_int, _d, _i64, _d, _d, _dp,
+                                      _vp, _u64, C.c_int, C.c_int, _dp, _vp, _dp,
+                                      C.POINTER(SiInfo), _vp])
+_sig("mbl_twist_expect_batched", _i32, [_vp, _vp, _vp, C.c_int, _dp, _vp])
+
+
+class Batch:
+    """Workspace for R realizations of one L solved in lockstep. Batched
+    vectors are (n, R) row-major tensors: element (i, r) at i * R + r."""
+
+    def __init__(self, basis: Basis, R: int, mmax: int = 0, nevmax: int = 0):
+        h = C.c_void_p()
+        _check(lib.mbl_batch_create(basis.handle, int(R), int(mmax), int(nevmax), C.byref(h)),
+               "mbl_batch_create", warn_ok=False)
+        self._h = h
+        self.basis = basis
+        self.R = int(R)
+        self.mmax = int(mmax)
+        self.nevmax = int(nevmax)
+        b = C.c_int64()
+        _check(lib.mbl_batch_bytes(h, C.byref(b)), "mbl_batch_bytes")
+        self.bytes = int(b.value)
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        if getattr(self, "_h", None) and lib is not None:
+            try:
+                lib.mbl_batch_free(self._h)
+            except Exception:   # interpreter shutdown
+                pass
+            self._h = None
+
+
+def _fields_matrix(h_list, R, L):
+    H = np.ascontiguousarray(np.asarray(h_list, dtype=np.float64).reshape(R, L))
+    return H, H.ctypes.data_as(_dp)
+
+
+def apply_H_batched(basis: Basis, batch: Batch, fields, sigmas, x, y=None, stream=None):
+    """y[:, r] = (H_r - sigma_r) x[:, r] for the (n, R) interleaved x."""
+    import torch
+    if x.dtype not in (torch.float64, torch.float32):
+        raise ValueError("x must be float64 or float32")
+    _need_cuda(x, x.dtype, basis.n * batch.R, "x")
+    if y is None:
+        y = torch.empty_like(x)
+    _need_cuda(y, x.dtype, basis.n * batch.R, "y")
+    H, hp = _fields_matrix(fields, batch.R, basis.L)
+    sg, sp = _f64(sigmas)
+    fn = lib.mbl_apply_H_batched if x.dtype == torch.float64 else lib.mbl_apply_H_batched_f32
+    _check(fn(basis.handle, batch.handle, hp, sp, _ptr(x), _ptr(y), _stream(stream)),
+           "mbl_apply_H_batched")
+    return y
+
+
+def minres_solve_batched(basis: Basis, batch: Batch, fields, sigmas, b, x=None, tol=1e-12,
+                         kmax=10_000_000, precision="fp64", precond="row", stream=None):
+    import torch
+    _need_cuda(b, torch.float64, basis.n * batch.R, "b")
+    if x is None:
+        x = torch.zeros_like(b)
+    H, hp = _fields_matrix(fields, batch.R, basis.L)
+    sg, sp = _f64(sigmas)
+    its = (C.c_int64 * batch.R)()
+    phi = np.zeros(batch.R)
+    st = lib.mbl_minres_solve_batched(basis.handle, batch.handle, hp, sp, _ptr(b), _ptr(x),
+                                      float(tol), int(kmax), PRECISION[precision], PRECOND[precond],
+                                      its, phi.ctypes.data_as(_dp), _stream(stream))
+    _check(st, "mbl_minres_solve_batched")
+    return x, np.array(list(its), dtype=np.int64), phi, st
+
+
+@dataclass
+class BatchEigResult:
+    status: int
+    evals: np.ndarray        # (R, nev)
+    evecs: object            # torch (nev, n, R)
+    resid: np.ndarray        # (R, nev)
+    steps: np.ndarray        # (R,)
+    nconv: np.ndarray        # (R,)
+    minres_iters: int        # whole batch
+    max_rel_resid: np.ndarray
+    seconds: float
+
+
+def si_lanczos_batched(basis: Basis, batch: Batch, fields, sigmas, nev: int, mmax: int | None = None,
+                       minres_tol=1e-12, minres_kmax=10_000_000, eig_tol=1e-10, gap_tol=1e-5,
+                       escale=None, v0=None, seed=0, precision="fp64", precond="row",
+                       stream=None) -> BatchEigResult:
+    import torch
+    R, n = batch.R, basis.n
+    if mmax is None:
+        mmax = min(batch.mmax, 3 * nev + 40)
+    H, hp = _fields_matrix(fields, R, basis.L)
+    sg, sp = _f64(sigmas)
+    es = None
+    if escale is not None:
+        esa, es = _f64(escale)
+    if v0 is not None:
+        _need_cuda(v0, torch.float64, n * R, "v0")
+    U = torch.empty((nev, n, R), dtype=torch.float64, device="cuda")
+    evals = np.zeros(R * nev)
+    resid = np.zeros(R * nev)
+    info = (SiInfo * R)()
+    st = lib.mbl_si_lanczos_batched(basis.handle, batch.handle, hp, sp, int(nev), int(mmax),
+                                    float(minres_tol), int(minres_kmax), float(eig_tol),
+                                    float(gap_tol), es, _ptr(v0) if v0 is not None else None,
+                                    int(seed) & (2**64 - 1), PRECISION[precision],
+                                    PRECOND[precond], evals.ctypes.data_as(_dp), _ptr(U),
+                                    resid.ctypes.data_as(_dp), info, _stream(stream))
+    _check(st, "mbl_si_lanczos_batched")
+    return BatchEigResult(st, evals.reshape(R, nev), U, resid.reshape(R, nev),
+                          np.array([i.steps for i in info]), np.array([i.nconv for i in info]),
+                          int(info[0].minres_iters), np.array([i.max_rel_resid for i in info]),
+                          float(info[0].seconds))
+
+
+def twist_expect_batched(basis: Basis, batch: Batch, U, stream=None) -> np.ndarray:
+    """z[r, t] for the (nev, n, R) interleaved eigenvector blocks."""
+    import torch
+    if U.dim() == 2:
+        U = U[None]
+    _need_cuda(U, torch.float64, None, "U")
+    nvec = U.shape[0]
+    z = np.zeros(batch.R * nvec * 2)
+    _check(lib.mbl_twist_expect_batched(basis.handle, batch.handle, _ptr(U), nvec,
+                                        z.ctypes.data_as(_dp), _stream(stream)),
+           "mbl_twist_expect_batched")
+    z = z.reshape(batch.R, nvec, 2)
+    return z[..., 0] + 1j * z[..., 1]

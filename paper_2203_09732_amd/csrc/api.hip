@@ -124,6 +124,7 @@ static void free_ws(mbl_workspace_s* w) {
   hipFree(w->partials2);
   hipFree(w->red_out);
   hipFree(w->state);
+  hipFree(w->sync);
   if (w->h_state) hipHostFree(w->h_state);
   if (w->h_red) hipHostFree(w->h_red);
   for (int i = 0; i < 2; ++i)
@@ -169,6 +170,7 @@ static mbl_status create_ws(mbl_basis_s* b, int mmax, int precision, bool minres
   A(&w->partials2, std::max<size_t>((size_t)kMaxPartials * 64, (size_t)512 * (mmax + 1)));
   A(&w->red_out, 256);
   A(&w->state, 2);
+  A(&w->sync, 4);
   if (st == MBL_OK) {
     if (hipHostMalloc((void**)&w->h_state, 4 * sizeof(MinresState)) != hipSuccess ||
         hipHostMalloc((void**)&w->h_red, 256 * sizeof(double)) != hipSuccess) {

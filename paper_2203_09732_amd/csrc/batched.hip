@@ -1,0 +1,1455 @@
+// Batched form: R disorder realizations of one chain length L solved in
+// lockstep. Vectors are interleaved, element (i, r) at i * R + r, so every
+// gather of a neighbour row fetches R contiguous values, and the index work
+// of a row (its state, neighbour ranks, block offsets) is shared by all R
+// realizations.
+//
+// Lane mapping (R a power of two, 2 <= R <= 32): PR = R / 2 lanes per row,
+// each lane owns the realization pair (2p, 2p + 1) and moves it with one
+// 8- or 16-byte access; a wavefront covers RPW = 64 / PR consecutive rows of
+// one chunk per step. Each realization keeps its own fields, shift, MINRES
+// scalars and done flag; per-realization dot products are reduced per
+// workgroup and then by one workgroup per realization, in a fixed order.
+#include "rows.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <vector>
+
+namespace mbl {
+
+constexpr int kBWG = 1024;   // threads per workgroup of the batched row kernels
+constexpr int kBMaxR = 32;
+constexpr int kBGrid = 512;  // upper bound on workgroups (partials per realization)
+
+template <typename T> struct Pair;
+template <> struct Pair<double> { using type = double2; };
+template <> struct Pair<float> { using type = float2; };
+
+// Per-realization MINRES state, double-buffered by iteration parity.
+struct BState {
+  double beta_prev, beta, c, s, dhat, eps, phi;
+  double alpha;                 // alpha_k of the current iteration
+  double d_inv_beta, d_delta, d_eps, d_inv_gamma, d_tau;   // d/x update coefficients
+  int64_t k;
+  int32_t done, bad;
+};
+
+struct BatchDev {
+  const double* h;     // R x L fields
+  const double* c0;    // R: L/4 + (1/2) sum h - sigma
+  int R;
+};
+
+// LDS: per-realization nibble tables, then the basis tables.
+__host__ __device__ constexpr size_t blds_bytes(int R, int L, int nlo) {
+  return (size_t)R * (((L + 3) >> 2) * 16) * sizeof(double) + (size_t)R * sizeof(double) +
+         kLdsRed * kBMaxR * sizeof(double) + 2 * sizeof(uint16_t) * ((size_t)1 << nlo);
+}
+
+struct BTables {
+  const double* lut;    // [R][nnib][16]
+  const double* c0;     // [R]
+  double* red;          // [waves][R]
+  const uint16_t* rank;
+  const uint16_t* state;
+};
+
+__device__ __forceinline__ BTables bsetup(const DevBasis& B, const BatchDev& Q, unsigned char* smem) {
+  const int R = Q.R, nnib = (B.L + 3) >> 2;
+  double* lut = reinterpret_cast<double*>(smem);
+  double* c0 = lut + (size_t)R * nnib * 16;
+  double* red = c0 + R;
+  uint16_t* rank = reinterpret_cast<uint16_t*>(red + kLdsRed * kBMaxR);
+  uint16_t* state = rank + (1u << B.nlo);
+  for (int t = threadIdx.x; t < R * nnib * 16; t += blockDim.x) {
+    const int r = t / (nnib * 16), rem = t % (nnib * 16), k = rem >> 4, v = rem & 15;
+    double acc = 0.0;
+    for (int b = 0; b < 4; ++b) {
+      const int site = 4 * k + b;
+      if (site < B.L && ((v >> b) & 1)) acc += Q.h[r * B.L + site];
+    }
+    lut[t] = acc;
+  }
+  for (int t = threadIdx.x; t < R; t += blockDim.x) c0[t] = Q.c0[t];
+  const int words = (1 << B.nlo) >> 1;
+  const uint32_t* gr = reinterpret_cast<const uint32_t*>(B.lo_rank);
+  const uint32_t* gs = reinterpret_cast<const uint32_t*>(B.lo_state);
+  uint32_t* sr = reinterpret_cast<uint32_t*>(rank);
+  uint32_t* ss = reinterpret_cast<uint32_t*>(state);
+  for (int t = threadIdx.x; t < words; t += blockDim.x) {
+    sr[t] = gr[t];
+    ss[t] = gs[t];
+  }
+  return BTables{lut, c0, red, rank, state};
+}
+
+// a_aa - sigma_r for realization r
+template <int L>
+__device__ __forceinline__ double bdiag(const BTables& t, int r, uint32_t a, int nanti) {
+  constexpr int NNIB = (L + 3) >> 2;
+  const double* lr = t.lut + r * NNIB * 16;
+  double fv[NNIB];
+#pragma unroll
+  for (int k = 0; k < NNIB; ++k) fv[k] = lr[(k << 4) + ((a >> (4 * k)) & 15u)];
+  double f = 0.0;
+#pragma unroll
+  for (int k = 0; k < NNIB; ++k) f += fv[k];
+  return t.c0[r] - 0.5 * (double)nanti - f;
+}
+
+template <int L>
+__device__ __forceinline__ int bnanti(uint32_t a) {
+  constexpr uint32_t mask = (L == 32) ? 0xffffffffu : ((1u << L) - 1u);
+  return __popc(a ^ (((a << 1) | (a >> (L - 1))) & mask));
+}
+
+// Off-diagonal sums for the lane's realization pair of one row.
+template <typename T, int L, int NLO>
+__device__ __forceinline__ void boffdiag(const DevBasis& B, const BTables& t,
+                                         const typename Pair<T>::type* __restrict__ x2,
+                                         uint32_t hi, uint32_t lo, uint32_t j, uint32_t block0,
+                                         int PR, int p, double& o0, double& o1) {
+  using T2 = typename Pair<T>::type;
+  constexpr int NHI = L - NLO;
+  constexpr int NLB = NLO - 1 > 0 ? NLO - 1 : 1;
+  constexpr int NHB = NHI - 1 > 0 ? NHI - 1 : 1;
+  const uint32_t hb_bnd = uni(B.hi_off[hi ^ 1u]);
+  const uint32_t hb_wrap = uni(B.hi_off[hi ^ (1u << (NHI - 1))]);
+  uint32_t hb[NHB];
+#pragma unroll
+  for (int b = 0; b + 1 < NHI; ++b) hb[b] = uni(B.hi_off[hi ^ (3u << b)]);
+  uint32_t r[NLB];
+#pragma unroll
+  for (int b = 0; b + 1 < NLO; ++b) r[b] = t.rank[lo ^ (3u << b)];
+  const uint32_t r_bnd = t.rank[lo ^ (1u << (NLO - 1))];
+  const uint32_t r_wrap = t.rank[lo ^ 1u];
+  const T2 zero = {(T)0, (T)0};
+  T2 v[NLB];
+#pragma unroll
+  for (int b = 0; b + 1 < NLO; ++b) {
+    v[b] = zero;
+    if (((lo >> b) ^ (lo >> (b + 1))) & 1u) v[b] = x2[((size_t)block0 + r[b]) * PR + p];
+  }
+  T2 v_bnd = zero;
+  if (((lo >> (NLO - 1)) ^ hi) & 1u) v_bnd = x2[((size_t)hb_bnd + r_bnd) * PR + p];
+  T2 vh[NHB];
+#pragma unroll
+  for (int b = 0; b + 1 < NHI; ++b) {
+    vh[b] = zero;
+    if (((hi >> b) ^ (hi >> (b + 1))) & 1u) vh[b] = x2[((size_t)hb[b] + j) * PR + p];
+  }
+  T2 v_wrap = zero;
+  if (((hi >> (NHI - 1)) ^ lo) & 1u) v_wrap = x2[((size_t)hb_wrap + r_wrap) * PR + p];
+  double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+  for (int b = 0; b + 1 < NLO; ++b) {
+    a0 += (double)v[b].x;
+    a1 += (double)v[b].y;
+  }
+  a0 += (double)v_bnd.x;
+  a1 += (double)v_bnd.y;
+#pragma unroll
+  for (int b = 0; b + 1 < NHI; ++b) {
+    a0 += (double)vh[b].x;
+    a1 += (double)vh[b].y;
+  }
+  a0 += (double)v_wrap.x;
+  a1 += (double)v_wrap.y;
+  o0 = a0;
+  o1 = a1;
+}
+
+// Visit this wave's rows: body(row, hi, lo, j, block0, a, p) for lanes with a
+// valid row. Chunks are grid-strided over waves; a chunk is walked RPW rows
+// at a time.
+template <typename Body>
+__device__ __forceinline__ void bfor_rows(const DevBasis& B, const BTables& t, int R, Body body) {
+  const int PR = R >> 1, RPW = 64 / PR;
+  const uint32_t lane = threadIdx.x & 63u;
+  const int p = lane % PR;
+  const uint32_t slot = lane / PR;
+  for_chunks(B.nchunks, [&](uint32_t c) {
+    const uint4 ch = B.chunks[c];
+    const uint32_t hi = uni(ch.x), j0 = uni(ch.y), cnt = uni(ch.z), row0 = uni(ch.w);
+    const uint32_t coff = uni(B.lo_coff[B.half - __popc(hi)]);
+    for (uint32_t s0 = 0; s0 < cnt; s0 += RPW) {
+      const uint32_t rl = s0 + slot;
+      if (rl < cnt) {
+        const uint32_t j = j0 + rl;
+        const uint32_t lo = t.state[coff + j];
+        body(row0 + rl, hi, lo, j, row0 - j0, (hi << B.nlo) | lo, p);
+      }
+    }
+  });
+}
+
+// Per-realization block reduction of (acc0, acc1) for pair p; thread r < R of
+// the workgroup ends with the sum for realization r (returned), others 0.
+__device__ __forceinline__ double bblock_sum(double acc0, double acc1, double* red, int R) {
+  const int PR = R >> 1;
+#pragma unroll
+  for (int o = PR; o < 64; o <<= 1) {
+    acc0 += __shfl_xor(acc0, o, 64);
+    acc1 += __shfl_xor(acc1, o, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane < PR) {
+    red[wave * R + 2 * lane] = acc0;
+    red[wave * R + 2 * lane + 1] = acc1;
+  }
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x < R) {
+    const int nw = blockDim.x >> 6;
+    for (int w = 0; w < nw; ++w) s += red[w * R + threadIdx.x];
+  }
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// y = (H_r - sigma_r) x_r for every realization. MODE 1: partial sums of
+// x.y per realization; GUARD: skip realizations whose state is done.
+template <typename T, int MODE, bool GUARD, int L, int NLO>
+__global__ __launch_bounds__(kBWG) void k_bapply(DevBasis B, BatchDev Q, const BState* S,
+                                                 const T* __restrict__ x, T* __restrict__ y,
+                                                 double* __restrict__ partials) {
+  using T2 = typename Pair<T>::type;
+  const int R = Q.R, PR = R >> 1;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const BTables t = bsetup(B, Q, smem);
+  __syncthreads();
+  const T2* x2 = reinterpret_cast<const T2*>(x);
+  T2* y2 = reinterpret_cast<T2*>(y);
+  const int lane_p = (threadIdx.x & 63) % PR;
+  bool live = true;
+  if (GUARD) live = !(S[2 * lane_p].done && S[2 * lane_p + 1].done);
+  double acc0 = 0.0, acc1 = 0.0;
+  if (live) {
+    bfor_rows(B, t, R, [&](uint32_t row, uint32_t hi, uint32_t lo, uint32_t j, uint32_t block0,
+                           uint32_t a, int p) {
+      double o0, o1;
+      boffdiag<T, L, NLO>(B, t, x2, hi, lo, j, block0, PR, p, o0, o1);
+      const int na = bnanti<L>(a);
+      const double d0 = bdiag<L>(t, 2 * p, a, na), d1 = bdiag<L>(t, 2 * p + 1, a, na);
+      const T2 xv = x2[(size_t)row * PR + p];
+      T2 yv;
+      yv.x = (T)(d0 * (double)xv.x + 0.5 * o0);
+      yv.y = (T)(d1 * (double)xv.y + 0.5 * o1);
+      y2[(size_t)row * PR + p] = yv;
+      if (MODE == 1) {
+        acc0 += (double)xv.x * (double)yv.x;
+        acc1 += (double)xv.y * (double)yv.y;
+      }
+    });
+  }
+  if (MODE == 1) {
+    const double s = bblock_sum(acc0, acc1, t.red, R);
+    if (threadIdx.x < R) partials[(size_t)blockIdx.x * R + threadIdx.x] = s;
+  }
+}
+
+// r = rhs - (H_r - sigma_r) x in FP64; partials[(g * R + r) * 2 + {0, 1}] =
+// sum r^2 / m (row-norm or chosen preconditioner) and sum r^2.
+template <int L, int NLO>
+__global__ __launch_bounds__(kBWG) void k_bresidual(DevBasis B, BatchDev Q, int kind,
+                                                    const double* __restrict__ rhs,
+                                                    const double* __restrict__ x,
+                                                    double* __restrict__ res,
+                                                    double* __restrict__ partials) {
+  const int R = Q.R, PR = R >> 1;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const BTables t = bsetup(B, Q, smem);
+  __syncthreads();
+  const double2* x2 = reinterpret_cast<const double2*>(x);
+  const double2* b2 = reinterpret_cast<const double2*>(rhs);
+  double2* r2 = reinterpret_cast<double2*>(res);
+  double m0 = 0, m1 = 0, q0 = 0, q1 = 0;
+  bfor_rows(B, t, R, [&](uint32_t row, uint32_t hi, uint32_t lo, uint32_t j, uint32_t block0,
+                         uint32_t a, int p) {
+    double o0, o1;
+    boffdiag<double, L, NLO>(B, t, x2, hi, lo, j, block0, PR, p, o0, o1);
+    const int na = bnanti<L>(a);
+    const double d0 = bdiag<L>(t, 2 * p, a, na), d1 = bdiag<L>(t, 2 * p + 1, a, na);
+    const double2 xv = x2[(size_t)row * PR + p], bv = b2[(size_t)row * PR + p];
+    double2 rv;
+    rv.x = bv.x - (d0 * xv.x + 0.5 * o0);
+    rv.y = bv.y - (d1 * xv.y + 0.5 * o1);
+    r2[(size_t)row * PR + p] = rv;
+    m0 += rv.x * rv.x / precond_value(kind, d0, na);
+    m1 += rv.y * rv.y / precond_value(kind, d1, na);
+    q0 += rv.x * rv.x;
+    q1 += rv.y * rv.y;
+  });
+  const double sm = bblock_sum(m0, m1, t.red, R);
+  const double sq = bblock_sum(q0, q1, t.red, R);
+  if (threadIdx.x < R) {
+    partials[((size_t)blockIdx.x * R + threadIdx.x) * 2] = sm;
+    partials[((size_t)blockIdx.x * R + threadIdx.x) * 2 + 1] = sq;
+  }
+}
+
+// MINRES initialisation per realization from x0 = 0: z_0 = 0, z_1 = scale_r
+// src_r, q_1 = M_r^{-1} z_1, d = 0, x = 0; partial sums of q_1 . z_1.
+template <typename T, int L>
+__global__ __launch_bounds__(kBWG) void k_binit(DevBasis B, BatchDev Q, int kind,
+                                                const double* __restrict__ src,
+                                                const double* __restrict__ scale, T* z0, T* z1,
+                                                T* q1, T* d0, T* d1, T* x,
+                                                double* __restrict__ partials) {
+  using T2 = typename Pair<T>::type;
+  const int R = Q.R, PR = R >> 1;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const BTables t = bsetup(B, Q, smem);
+  __syncthreads();
+  const double2* s2 = reinterpret_cast<const double2*>(src);
+  double a0 = 0, a1 = 0;
+  const T2 zero = {(T)0, (T)0};
+  bfor_rows(B, t, R, [&](uint32_t row, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t a, int p) {
+    const size_t e = (size_t)row * PR + p;
+    const int na = bnanti<L>(a);
+    const double d0v = bdiag<L>(t, 2 * p, a, na), d1v = bdiag<L>(t, 2 * p + 1, a, na);
+    const double2 sv = s2[e];
+    T2 zt, qt;
+    zt.x = (T)(scale[2 * p] * sv.x);
+    zt.y = (T)(scale[2 * p + 1] * sv.y);
+    qt.x = (T)((double)zt.x / precond_value(kind, d0v, na));
+    qt.y = (T)((double)zt.y / precond_value(kind, d1v, na));
+    reinterpret_cast<T2*>(z0)[e] = zero;
+    reinterpret_cast<T2*>(z1)[e] = zt;
+    reinterpret_cast<T2*>(q1)[e] = qt;
+    reinterpret_cast<T2*>(d0)[e] = zero;
+    reinterpret_cast<T2*>(d1)[e] = zero;
+    reinterpret_cast<T2*>(x)[e] = zero;
+    a0 += (double)qt.x * (double)zt.x;
+    a1 += (double)qt.y * (double)zt.y;
+  });
+  const double s = bblock_sum(a0, a1, t.red, R);
+  if (threadIdx.x < R) partials[(size_t)blockIdx.x * R + threadIdx.x] = s;
+}
+
+// z_{k+1}, q_{k+1} and partial sums of q_{k+1} . z_{k+1}, for live realizations.
+template <typename T, int L>
+__global__ __launch_bounds__(kBWG) void k_bzq(DevBasis B, BatchDev Q, int kind,
+                                              const BState* __restrict__ S,
+                                              const T* __restrict__ p, const T* __restrict__ zk,
+                                              T* __restrict__ zkm1, T* __restrict__ qn,
+                                              double* __restrict__ partials) {
+  using T2 = typename Pair<T>::type;
+  const int R = Q.R, PR = R >> 1;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const BTables t = bsetup(B, Q, smem);
+  __syncthreads();
+  const int lp = (threadIdx.x & 63) % PR;
+  const BState s0 = S[2 * lp], s1 = S[2 * lp + 1];
+  const bool live0 = !s0.done, live1 = !s1.done;
+  const double c10 = 1.0 / s0.beta, c20 = s0.alpha / s0.beta, c30 = s0.beta / s0.beta_prev;
+  const double c11 = 1.0 / s1.beta, c21 = s1.alpha / s1.beta, c31 = s1.beta / s1.beta_prev;
+  double a0 = 0, a1 = 0;
+  if (live0 || live1) {
+    bfor_rows(B, t, R, [&](uint32_t row, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t a,
+                           int pp) {
+      const size_t e = (size_t)row * PR + pp;
+      const int na = bnanti<L>(a);
+      const T2 pv = reinterpret_cast<const T2*>(p)[e];
+      const T2 zv = reinterpret_cast<const T2*>(zk)[e];
+      T2 zo = reinterpret_cast<T2*>(zkm1)[e];
+      T2 qo = reinterpret_cast<T2*>(qn)[e];
+      if (live0) {
+        const double zn = c10 * (double)pv.x - c20 * (double)zv.x - c30 * (double)zo.x;
+        zo.x = (T)zn;
+        qo.x = (T)((double)zo.x / precond_value(kind, bdiag<L>(t, 2 * pp, a, na), na));
+        a0 += (double)qo.x * (double)zo.x;
+      }
+      if (live1) {
+        const double zn = c11 * (double)pv.y - c21 * (double)zv.y - c31 * (double)zo.y;
+        zo.y = (T)zn;
+        qo.y = (T)((double)zo.y / precond_value(kind, bdiag<L>(t, 2 * pp + 1, a, na), na));
+        a1 += (double)qo.y * (double)zo.y;
+      }
+      reinterpret_cast<T2*>(zkm1)[e] = zo;
+      reinterpret_cast<T2*>(qn)[e] = qo;
+    });
+  }
+  const double s = bblock_sum(a0, a1, t.red, R);
+  if (threadIdx.x < R) partials[(size_t)blockIdx.x * R + threadIdx.x] = s;
+}
+
+// One workgroup per realization: beta_1 and the initial state.
+__global__ void k_binit_state(const double* __restrict__ partials, int G, int R, double tol,
+                              int64_t kmax, BState* S0) {
+  __shared__ double red[kWavesPerWG];
+  const int r = blockIdx.x;
+  double v = 0;
+  for (int g = threadIdx.x; g < G; g += blockDim.x) v += partials[(size_t)g * R + r];
+  const double qz = block_sum_all(v, red);
+  if (threadIdx.x == 0) {
+    BState s{};
+    s.beta_prev = 1.0;
+    s.beta = sqrt(qz);
+    s.c = 1.0;
+    s.s = 0.0;
+    s.dhat = 0.0;
+    s.eps = 0.0;
+    s.phi = s.beta;
+    s.k = 0;
+    s.bad = !isfinite(s.beta);
+    s.done = s.bad || !(fabs(s.beta) >= tol && 0 < kmax);
+    S0[r] = s;
+  }
+}
+
+// One workgroup per realization: alpha_k from the apply partials.
+__global__ void k_balpha(const double* __restrict__ partials, int G, int R, BState* S) {
+  __shared__ double red[kWavesPerWG];
+  const int r = blockIdx.x;
+  if (S[r].done) return;
+  double v = 0;
+  for (int g = threadIdx.x; g < G; g += blockDim.x) v += partials[(size_t)g * R + r];
+  const double qp = block_sum_all(v, red);
+  if (threadIdx.x == 0) S[r].alpha = qp / (S[r].beta * S[r].beta);
+}
+
+// One workgroup per realization: beta_{k+1}, Givens rotation, d/x
+// coefficients, next state into Sout (carried unchanged once done).
+__global__ void k_bgivens(const double* __restrict__ partials, int G, int R, double tol,
+                          int64_t kmax, const BState* __restrict__ Sin, BState* __restrict__ Sout) {
+  __shared__ double red[kWavesPerWG];
+  const int r = blockIdx.x;
+  const BState si = Sin[r];
+  if (si.done) {
+    if (threadIdx.x == 0) {
+      BState so = si;
+      so.d_tau = 0.0;
+      Sout[r] = so;
+    }
+    return;
+  }
+  double v = 0;
+  for (int g = threadIdx.x; g < G; g += blockDim.x) v += partials[(size_t)g * R + r];
+  const double qz = block_sum_all(v, red);
+  if (threadIdx.x == 0) {
+    const double alpha = si.alpha, beta = si.beta;
+    const double beta_next = sqrt(qz);
+    const double delta = si.c * si.dhat + si.s * alpha;
+    const double gamma_hat = -si.s * si.dhat + si.c * alpha;
+    const double eps_next = si.s * beta_next;
+    const double dhat_next = si.c * beta_next;
+    const double gamma = sqrt(gamma_hat * gamma_hat + beta_next * beta_next);
+    const double c = gamma_hat / gamma, s = beta_next / gamma;
+    const double tau = c * si.phi, phi = -s * si.phi;
+    BState so = si;
+    so.d_inv_beta = 1.0 / beta;
+    so.d_delta = delta;
+    so.d_eps = si.eps;
+    so.d_inv_gamma = 1.0 / gamma;
+    so.d_tau = tau;
+    so.beta_prev = beta;
+    so.beta = beta_next;
+    so.c = c;
+    so.s = s;
+    so.dhat = dhat_next;
+    so.eps = eps_next;
+    so.phi = phi;
+    so.k = si.k + 1;
+    so.bad = !isfinite(phi) || !isfinite(alpha) || !isfinite(beta_next);
+    so.done = so.bad || !(fabs(phi) >= tol && so.k < kmax);
+    Sout[r] = so;
+  }
+}
+
+// d_k = (q_k / beta_k - delta_k d_{k-1} - eps_k d_{k-2}) / gamma_k, x += tau_k d_k
+// for the realizations that took step k (Sk is the state after step k; a
+// realization done before step k has d_tau = 0 and is left untouched).
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_bdx(int64_t n, int R, const BState* __restrict__ Sk,
+                                             const BState* __restrict__ Sprev,
+                                             const T* __restrict__ qk, const T* __restrict__ dkm1,
+                                             T* __restrict__ dkm2, T* __restrict__ x) {
+  __shared__ double co[kBMaxR][5];
+  __shared__ int act[kBMaxR];
+  if (threadIdx.x < R) {
+    const BState s = Sk[threadIdx.x];
+    co[threadIdx.x][0] = s.d_inv_beta;
+    co[threadIdx.x][1] = s.d_delta;
+    co[threadIdx.x][2] = s.d_eps;
+    co[threadIdx.x][3] = s.d_inv_gamma;
+    co[threadIdx.x][4] = s.d_tau;
+    act[threadIdx.x] = !Sprev[threadIdx.x].done;
+  }
+  __syncthreads();
+  const int64_t total = n * R;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e & (R - 1));
+    if (!act[r]) continue;
+    const double d = ((double)qk[e] * co[r][0] - co[r][1] * (double)dkm1[e] -
+                      co[r][2] * (double)dkm2[e]) * co[r][3];
+    const T dt = (T)d;
+    dkm2[e] = dt;
+    x[e] = (T)((double)x[e] + co[r][4] * (double)dt);
+  }
+}
+
+// per-realization reduction: out[r * nv + v] = sum_g partials[(g * R + r) * nv + v]
+__global__ void k_breduce(const double* __restrict__ partials, int G, int R, int nv,
+                          double* __restrict__ out) {
+  __shared__ double red[kWavesPerWG];
+  const int r = blockIdx.x / nv, v = blockIdx.x % nv;
+  double a = 0;
+  for (int g = threadIdx.x; g < G; g += blockDim.x) a += partials[((size_t)g * R + r) * nv + v];
+  const double s = block_sum_all(a, red);
+  if (threadIdx.x == 0) out[r * nv + v] = s;
+}
+
+// x64 += scale_r * e (interleaved)
+__global__ __launch_bounds__(kWG) void k_badd_scaled(int64_t n, int R, const double* __restrict__ scale,
+                                                     const float* __restrict__ e,
+                                                     double* __restrict__ x) {
+  const int64_t total = n * R;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] += scale[i & (R - 1)] * (double)e[i];
+}
+
+// ---------------------------------------------------------------------------
+// dense batched helpers for the Lanczos recurrences (interleaved n x R)
+
+// partials[(g * k + c) * R + r] = sum_i V_c[i, r] w[i, r] over this group's
+// rows, c in the tile [4 by, 4 by + 4) with c < k
+__global__ __launch_bounds__(kWG) void k_bmultidot(int64_t n, int R, const double* __restrict__ V,
+                                                   int64_t vstride, int k,
+                                                   const double* __restrict__ w,
+                                                   double* __restrict__ partials) {
+  constexpr int TC = 4;
+  __shared__ double red[kWavesPerWG][TC][kBMaxR];
+  const int c0 = blockIdx.y * TC;
+  const int nc = min(TC, k - c0);
+  // each thread owns one realization r = tid % R and rows strided by 256/R
+  const int r = threadIdx.x % R;
+  const int rows_per = blockDim.x / R;
+  const int rl = threadIdx.x / R;
+  double acc[TC] = {0, 0, 0, 0};
+  for (int64_t i = (int64_t)blockIdx.x * rows_per + rl; i < n; i += (int64_t)gridDim.x * rows_per) {
+    const double wi = w[i * R + r];
+#pragma unroll
+    for (int tc = 0; tc < TC; ++tc)
+      if (tc < nc) acc[tc] += V[(size_t)(c0 + tc) * vstride + i * R + r] * wi;
+  }
+  // reduce over lanes with the same r inside the wave
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int tc = 0; tc < TC; ++tc)
+    for (int o = R; o < 64; o <<= 1) acc[tc] += __shfl_xor(acc[tc], o, 64);
+  if (lane < R) {
+#pragma unroll
+    for (int tc = 0; tc < TC; ++tc) red[wave][tc][lane] = acc[tc];
+  }
+  __syncthreads();
+  if (threadIdx.x < nc * R) {
+    const int tc = threadIdx.x / R, rr = threadIdx.x % R;
+    double s = 0;
+    for (int wv = 0; wv < kWavesPerWG; ++wv) s += red[wv][tc][rr];
+    partials[((size_t)blockIdx.x * k + c0 + tc) * R + rr] = s;
+  }
+}
+
+// w[i, r] -= sum_{c < k} V_c[i, r] coef[c * R + r]
+__global__ __launch_bounds__(kWG) void k_bcgs_update(int64_t n, int R, const double* __restrict__ V,
+                                                     int64_t vstride, int k,
+                                                     const double* __restrict__ coef,
+                                                     double* __restrict__ w) {
+  extern __shared__ double sc[];
+  for (int e = threadIdx.x; e < k * R; e += blockDim.x) sc[e] = coef[e];
+  __syncthreads();
+  const int64_t total = n * R;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e % R);
+    double s = 0;
+    for (int c = 0; c < k; ++c) s += V[(size_t)c * vstride + e] * sc[c * R + r];
+    w[e] -= s;
+  }
+}
+
+// y[i, r] = a[r] * x[i, r] + b[r] * y[i, r]
+__global__ __launch_bounds__(kWG) void k_baxpby(int64_t n, int R, const double* __restrict__ a,
+                                                const double* __restrict__ x,
+                                                const double* __restrict__ b, double* y) {
+  const int64_t total = n * R;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e % R);
+    y[e] = a[r] * x[e] + b[r] * y[e];
+  }
+}
+
+// partials[(g * R + r)] = sum_i x[i, r] y[i, r]
+__global__ __launch_bounds__(kWG) void k_bdot(int64_t n, int R, const double* __restrict__ x,
+                                              const double* __restrict__ y,
+                                              double* __restrict__ partials) {
+  __shared__ double red[kWavesPerWG][kBMaxR];
+  const int r = threadIdx.x % R, rl = threadIdx.x / R, rows_per = blockDim.x / R;
+  double acc = 0;
+  for (int64_t i = (int64_t)blockIdx.x * rows_per + rl; i < n; i += (int64_t)gridDim.x * rows_per)
+    acc += x[i * R + r] * y[i * R + r];
+  for (int o = R; o < 64; o <<= 1) acc += __shfl_xor(acc, o, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane < R) red[wave][lane] = acc;
+  __syncthreads();
+  if (threadIdx.x < R) {
+    double s = 0;
+    for (int wv = 0; wv < kWavesPerWG; ++wv) s += red[wv][threadIdx.x];
+    partials[(size_t)blockIdx.x * R + threadIdx.x] = s;
+  }
+}
+
+// U_t[i, r] = sum_c V_c[i, r] Y[(r * k + c) * nev + t]   (Y per realization)
+__global__ __launch_bounds__(kWG) void k_britz(int64_t n, int R, const double* __restrict__ V,
+                                               int64_t vstride, int k,
+                                               const double* __restrict__ Y, int nev,
+                                               double* __restrict__ U, int64_t ustride) {
+  const int t = blockIdx.y;
+  const int64_t total = n * R;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e % R);
+    double s = 0;
+    for (int c = 0; c < k; ++c) s += V[(size_t)c * vstride + e] * Y[((size_t)r * k + c) * nev + t];
+    U[(size_t)t * ustride + e] = s;
+  }
+}
+
+
+// twist partial sums per (vector t, realization r): partials[((t * G + g) * R + r) * 2 + {0, 1}]
+struct BTwistTab {
+  double c[2 * kMaxL];
+  double s[2 * kMaxL];
+};
+template <int L>
+__global__ __launch_bounds__(kBWG) void k_btwist(DevBasis B, BatchDev Q, BTwistTab T,
+                                                 const double* __restrict__ psi, int64_t vstride,
+                                                 double* __restrict__ partials) {
+  const int R = Q.R, PR = R >> 1;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const BTables t = bsetup(B, Q, smem);
+  __syncthreads();
+  const double2* v2 = reinterpret_cast<const double2*>(psi + (size_t)blockIdx.y * vstride);
+  double r0 = 0, i0 = 0, r1 = 0, i1 = 0;
+  constexpr int base = (L * (L + 1)) / 2;
+  bfor_rows(B, t, R, [&](uint32_t row, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t a, int p) {
+    int sum = 0;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      uint32_t w = 0;
+      for (int q = 0; q < 32; ++q)
+        if (((q + 1) >> k) & 1) w |= (1u << q);
+      sum += __popc(a & w) << k;
+    }
+    int m = (2 * sum - base) % (2 * L);
+    if (m < 0) m += 2 * L;
+    const double2 v = v2[(size_t)row * PR + p];
+    r0 += v.x * v.x * T.c[m];
+    i0 += v.x * v.x * T.s[m];
+    r1 += v.y * v.y * T.c[m];
+    i1 += v.y * v.y * T.s[m];
+  });
+  const double sr = bblock_sum(r0, r1, t.red, R);
+  const double si = bblock_sum(i0, i1, t.red, R);
+  if (threadIdx.x < R) {
+    const size_t g = ((size_t)blockIdx.y * gridDim.x + blockIdx.x) * R + threadIdx.x;
+    partials[2 * g] = sr;
+    partials[2 * g + 1] = si;
+  }
+}
+
+}  // namespace mbl
+
+// ===========================================================================
+// host side
+
+struct mbl_batch_s {
+  mbl_basis basis = nullptr;
+  int R = 0, mmax = 0, nevmax = 0;
+  int64_t n = 0, bytes = 0;
+  double* h = nullptr;       // R * L
+  double* c0 = nullptr;      // R
+  mbl::BState* S = nullptr;  // 2 * R
+  double* z[2] = {nullptr, nullptr};
+  double* q[2] = {nullptr, nullptr};
+  double* d[2] = {nullptr, nullptr};
+  double* p = nullptr;
+  double* e = nullptr;
+  double* r64 = nullptr;
+  double* t64 = nullptr;
+  double* w = nullptr;
+  double* x = nullptr;
+  double* V = nullptr;       // (mmax + 1) blocks of n * R
+  double* coef = nullptr;    // (mmax + 1) * R
+  double* ycoef = nullptr;   // R * (mmax + 1) * nevmax
+  double* partials1 = nullptr;
+  double* partials2 = nullptr;
+  double* red = nullptr;     // R * 64
+  double* scale = nullptr;   // R
+  double* scale2 = nullptr;  // R
+  mbl::BState* h_state = nullptr;   // pinned, 4 * R
+  double* h_red = nullptr;          // pinned, R * 64
+  double* h_stage = nullptr;        // pinned, R * (L + 1) + 4 R
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  size_t part_elems = 0;
+  std::vector<double> last_up;      // host copy of the last uploaded (h, c0)
+};
+
+namespace mbl {
+
+static int bgrid(const mbl_basis_s* b) {
+  int g = (b->nchunks + (kBWG / 64) - 1) / (kBWG / 64);
+  g = std::max(1, std::min(g, kBGrid));
+  return g >= 64 ? (g / 8) * 8 : g;   // whole XCD slices once the grid is large
+}
+
+static bool batched_split_supported(const mbl_basis_s* b) {
+  switch (b->L * 64 + b->nlo) {
+#define MBL_CASE(LL, NN) case LL * 64 + NN:
+    MBL_FAST_SPLITS(MBL_CASE)
+#undef MBL_CASE
+    return true;
+    default:
+      return false;
+  }
+}
+
+#define MBL_BDISPATCH(KERNEL_TEMPLATE_CALL)                                   \
+  switch (b->L * 64 + b->nlo) {                                              \
+    MBL_FAST_SPLITS(KERNEL_TEMPLATE_CALL)                                    \
+    default:                                                                 \
+      set_error("batched form has no instance for this (L, lo_bits)");      \
+      return MBL_ERR_ARG;                                                    \
+  }
+
+template <typename T, int MODE, bool GUARD>
+static mbl_status launch_bapply(const mbl_basis_s* b, const BatchDev& Q, const BState* S,
+                                const T* x, T* y, double* partials, hipStream_t s) {
+  const size_t lds = blds_bytes(Q.R, b->L, b->nlo);
+  const dim3 g(bgrid(b)), blk(kBWG);
+  const DevBasis B = b->dev();
+#define MBL_CASE(LL, NN)                                                                    \
+  case LL * 64 + NN:                                                                       \
+    hipLaunchKernelGGL((k_bapply<T, MODE, GUARD, LL, NN>), g, blk, lds, s, B, Q, S, x, y,  \
+                       partials);                                                          \
+    break;
+  MBL_BDISPATCH(MBL_CASE)
+#undef MBL_CASE
+  MBL_HIP(hipGetLastError());
+  return MBL_OK;
+}
+
+static mbl_status launch_bresidual(const mbl_basis_s* b, const BatchDev& Q, int kind,
+                                   const double* rhs, const double* x, double* res,
+                                   double* partials, hipStream_t s) {
+  const size_t lds = blds_bytes(Q.R, b->L, b->nlo);
+  const dim3 g(bgrid(b)), blk(kBWG);
+  const DevBasis B = b->dev();
+#define MBL_CASE(LL, NN)                                                                       \
+  case LL * 64 + NN:                                                                          \
+    hipLaunchKernelGGL((k_bresidual<LL, NN>), g, blk, lds, s, B, Q, kind, rhs, x, res,       \
+                       partials);                                                             \
+    break;
+  MBL_BDISPATCH(MBL_CASE)
+#undef MBL_CASE
+  MBL_HIP(hipGetLastError());
+  return MBL_OK;
+}
+
+template <typename T>
+static mbl_status launch_binit(const mbl_basis_s* b, const BatchDev& Q, int kind,
+                               const double* src, const double* scale, T* z0, T* z1, T* q1, T* d0,
+                               T* d1, T* x, double* partials, hipStream_t s) {
+  const size_t lds = blds_bytes(Q.R, b->L, b->nlo);
+  const dim3 g(bgrid(b)), blk(kBWG);
+  const DevBasis B = b->dev();
+#define MBL_CASE(LL, NN)                                                                        \
+  case LL * 64 + NN:                                                                           \
+    hipLaunchKernelGGL((k_binit<T, LL>), g, blk, lds, s, B, Q, kind, src, scale, z0, z1, q1,  \
+                       d0, d1, x, partials);                                                   \
+    break;
+  MBL_BDISPATCH(MBL_CASE)
+#undef MBL_CASE
+  MBL_HIP(hipGetLastError());
+  return MBL_OK;
+}
+
+template <typename T>
+static mbl_status launch_bzq(const mbl_basis_s* b, const BatchDev& Q, int kind, const BState* S,
+                             const T* p, const T* zk, T* zkm1, T* qn, double* partials,
+                             hipStream_t s) {
+  const size_t lds = blds_bytes(Q.R, b->L, b->nlo);
+  const dim3 g(bgrid(b)), blk(kBWG);
+  const DevBasis B = b->dev();
+#define MBL_CASE(LL, NN)                                                                        \
+  case LL * 64 + NN:                                                                           \
+    hipLaunchKernelGGL((k_bzq<T, LL>), g, blk, lds, s, B, Q, kind, S, p, zk, zkm1, qn,        \
+                       partials);                                                              \
+    break;
+  MBL_BDISPATCH(MBL_CASE)
+#undef MBL_CASE
+  MBL_HIP(hipGetLastError());
+  return MBL_OK;
+}
+
+static int bflat_grid(int64_t total) {
+  int64_t g = (total + kWG - 1) / kWG;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, 4096));
+}
+
+// upload fields and shifts of the R realizations (c0_r = L/4 + sum h_r / 2 - sigma_r)
+static mbl_status bupload(mbl_batch_s* bw, const double* h_host, const double* sigma_host,
+                          hipStream_t s) {
+  const int R = bw->R, L = bw->basis->L;
+  std::vector<double> up((size_t)R * (L + 1));
+  std::copy(h_host, h_host + (size_t)R * L, up.begin());
+  for (int r = 0; r < R; ++r) {
+    double sh = 0;
+    for (int j = 0; j < L; ++j) sh += h_host[(size_t)r * L + j];
+    up[(size_t)R * L + r] = 0.25 * L + 0.5 * sh - sigma_host[r];
+  }
+  if (up == bw->last_up) return MBL_OK;   // already on the device
+  double* st = bw->h_stage;
+  MBL_HIP(hipStreamSynchronize(s));   // staging buffer reuse
+  std::copy(up.begin(), up.end(), st);
+  bw->last_up = up;
+  MBL_HIP(hipMemcpyAsync(bw->h, st, sizeof(double) * R * L, hipMemcpyHostToDevice, s));
+  MBL_HIP(hipMemcpyAsync(bw->c0, st + (size_t)R * L, sizeof(double) * R, hipMemcpyHostToDevice,
+                         s));
+  return MBL_OK;
+}
+
+// per-realization sums to host: out[r * nv + v] = sum_g partials[((g * R) + r) * nv + v]
+static mbl_status breduce_host(mbl_batch_s* bw, const double* partials, int G, int nv,
+                               double* out, hipStream_t s) {
+  const int R = bw->R;
+  hipLaunchKernelGGL(k_breduce, dim3(R * nv), dim3(kWG), 0, s, partials, G, R, nv, bw->red);
+  MBL_HIP(hipGetLastError());
+  MBL_HIP(hipMemcpyAsync(bw->h_red, bw->red, sizeof(double) * R * nv, hipMemcpyDeviceToHost, s));
+  MBL_HIP(hipStreamSynchronize(s));
+  std::copy(bw->h_red, bw->h_red + R * nv, out);
+  return MBL_OK;
+}
+
+// Alg. 2 on all realizations, from x0 = 0 with z_1 = scale_r src_r (a zero
+// scale makes realization r done at once). x: T, n * R.
+template <typename T>
+static mbl_status bminres_core(mbl_basis_s* b, mbl_batch_s* bw, const BatchDev& Q, int precond,
+                               const double* src, const double* scale_dev, T* x, double tol,
+                               int64_t kmax, hipStream_t s, std::vector<BState>& fin) {
+  const int R = bw->R;
+  const int64_t n = b->n;
+  T* Z[2] = {(T*)bw->z[0], (T*)bw->z[1]};
+  T* Qv[2] = {(T*)bw->q[0], (T*)bw->q[1]};
+  T* D[2] = {(T*)bw->d[0], (T*)bw->d[1]};
+  T* P = (T*)bw->p;
+  const int G = bgrid(b);
+  BState* S = bw->S;
+  MBL_TRY(launch_binit<T>(b, Q, precond, src, scale_dev, Z[0], Z[1], Qv[1], D[0], D[1], x,
+                          bw->partials2, s));
+  hipLaunchKernelGGL(k_binit_state, dim3(R), dim3(kWG), 0, s, bw->partials2, G, R, tol, kmax, S);
+  MBL_HIP(hipGetLastError());
+  const int FG = bflat_grid(n * R);
+  const int64_t kChunkIters = 32;
+  int64_t issued = 0;
+  int pending = 0, slot = 0;
+  bool done = false;
+  auto check = [&](int which) -> mbl_status {
+    MBL_HIP(hipEventSynchronize(bw->ev[which]));
+    bool all = true;
+    for (int r = 0; r < R; ++r) all = all && bw->h_state[which * R + r].done;
+    if (all) done = true;
+    fin.assign(bw->h_state + which * R, bw->h_state + which * R + R);
+    return MBL_OK;
+  };
+  while (!done && issued < kmax) {
+    const int64_t k_end = std::min(kmax, issued + kChunkIters);
+    for (int64_t k = issued + 1; k <= k_end; ++k) {
+      BState* Sin = S + ((k - 1) & 1) * R;
+      BState* Sout = S + (k & 1) * R;
+      MBL_TRY((launch_bapply<T, 1, true>(b, Q, Sin, Qv[k & 1], P, bw->partials1, s)));
+      hipLaunchKernelGGL(k_balpha, dim3(R), dim3(kWG), 0, s, bw->partials1, G, R, Sin);
+      MBL_TRY(launch_bzq<T>(b, Q, precond, Sin, P, Z[k & 1], Z[(k + 1) & 1], Qv[(k + 1) & 1],
+                            bw->partials2, s));
+      hipLaunchKernelGGL(k_bgivens, dim3(R), dim3(kWG), 0, s, bw->partials2, G, R, tol, kmax, Sin,
+                         Sout);
+      hipLaunchKernelGGL((k_bdx<T>), dim3(FG), dim3(kWG), 0, s, n, R, Sout, Sin, Qv[k & 1],
+                         D[(k - 1) & 1], D[k & 1], x);
+    }
+    MBL_HIP(hipGetLastError());
+    issued = k_end;
+    MBL_HIP(hipMemcpyAsync(bw->h_state + slot * R, S + (issued & 1) * R, sizeof(BState) * R,
+                           hipMemcpyDeviceToHost, s));
+    MBL_HIP(hipEventRecord(bw->ev[slot], s));
+    ++pending;
+    if (pending == 2) {
+      MBL_TRY(check(slot ^ 1));
+      --pending;
+    }
+    slot ^= 1;
+  }
+  if (pending > 0) MBL_TRY(check(slot ^ 1));
+  for (const BState& st : fin)
+    if (st.bad) {
+      set_error("batched MINRES met a non-finite value");
+      return MBL_ERR_NUMERIC;
+    }
+  return MBL_OK;
+}
+
+// Batched MINRES for (H_r - sigma_r) x_r = b_r from x0 = 0 (fields and shifts
+// already uploaded). FP64, or FP32 inner solves with FP64 residual restarts.
+// active[r] = 0 skips realization r (its x is left at 0).
+static mbl_status bminres_run(mbl_basis_s* b, mbl_batch_s* bw, int precision, int precond,
+                              const double* rhs, double* x, double tol, int64_t kmax,
+                              const std::vector<int>& active, hipStream_t s,
+                              std::vector<int64_t>& iters, std::vector<double>& phi) {
+  const int R = bw->R;
+  const int64_t n = b->n;
+  BatchDev Q{bw->h, bw->c0, R};
+  iters.assign(R, 0);
+  phi.assign(R, 0.0);
+  std::vector<double> sc(R);
+  if (precision == MBL_FP64) {
+    for (int r = 0; r < R; ++r) sc[r] = active[r] ? 1.0 : 0.0;
+    MBL_HIP(hipMemcpyAsync(bw->scale, sc.data(), sizeof(double) * R, hipMemcpyHostToDevice, s));
+    std::vector<BState> fin;
+    MBL_TRY(bminres_core<double>(b, bw, Q, precond, rhs, bw->scale, x, tol, kmax, s, fin));
+    for (int r = 0; r < R; ++r) {
+      iters[r] = fin[r].k;
+      phi[r] = std::fabs(fin[r].phi);
+    }
+    return MBL_OK;
+  }
+  // FP32 inner solves: x64 starts at 0, restart from the FP64 residual
+  const double eta = 1e-6;
+  MBL_HIP(hipMemsetAsync(x, 0, sizeof(double) * n * R, s));
+  std::vector<double> sums(2 * R);
+  for (int cycle = 0; cycle < 200; ++cycle) {
+    MBL_TRY(launch_bresidual(b, Q, precond, rhs, x, bw->r64, bw->partials1, s));
+    MBL_TRY(breduce_host(bw, bw->partials1, bgrid(b), 2, sums.data(), s));
+    bool any = false;
+    double worst = 0;
+    for (int r = 0; r < R; ++r) {
+      const double rM = std::sqrt(sums[2 * r]);
+      phi[r] = rM;
+      const bool go = active[r] && rM >= tol && iters[r] < kmax;
+      sc[r] = go ? 1.0 / rM : 0.0;
+      bw->h_stage[r] = go ? rM : 0.0;
+      any = any || go;
+      if (go) worst = std::max(worst, tol / rM);
+      if (!std::isfinite(rM) && active[r]) {
+        set_error("non-finite residual in batched FP32-inner MINRES");
+        return MBL_ERR_NUMERIC;
+      }
+    }
+    if (!any) break;
+    MBL_HIP(hipMemcpyAsync(bw->scale, sc.data(), sizeof(double) * R, hipMemcpyHostToDevice, s));
+    MBL_HIP(hipMemcpyAsync(bw->scale2, bw->h_stage, sizeof(double) * R, hipMemcpyHostToDevice, s));
+    const double inner_tol = std::max(eta, 0.5 * worst);
+    std::vector<BState> fin;
+    MBL_TRY(bminres_core<float>(b, bw, Q, precond, bw->r64, bw->scale, (float*)bw->e, inner_tol,
+                                kmax, s, fin));
+    for (int r = 0; r < R; ++r) iters[r] += fin[r].k;
+    hipLaunchKernelGGL(k_badd_scaled, dim3(bflat_grid(n * R)), dim3(kWG), 0, s, n, R, bw->scale2,
+                       (const float*)bw->e, x);
+    MBL_HIP(hipGetLastError());
+    MBL_HIP(hipStreamSynchronize(s));
+  }
+  return MBL_OK;
+}
+
+static mbl_status bdot_host(mbl_batch_s* bw, int64_t n, const double* x, const double* y,
+                            double* out, hipStream_t s) {
+  const int R = bw->R;
+  const int G = std::max<int>(1, std::min<int64_t>(512, (n + 255) / 256));
+  hipLaunchKernelGGL(k_bdot, dim3(G), dim3(kWG), 0, s, n, R, x, y, bw->partials1);
+  MBL_HIP(hipGetLastError());
+  return breduce_host(bw, bw->partials1, G, 1, out, s);
+}
+
+static mbl_status baxpby(mbl_batch_s* bw, int64_t n, const std::vector<double>& a, const double* x,
+                         const std::vector<double>& bb, double* y, hipStream_t s) {
+  const int R = bw->R;
+  MBL_HIP(hipStreamSynchronize(s));
+  std::copy(a.begin(), a.end(), bw->h_stage);
+  std::copy(bb.begin(), bb.end(), bw->h_stage + R);
+  MBL_HIP(hipMemcpyAsync(bw->scale, bw->h_stage, sizeof(double) * R, hipMemcpyHostToDevice, s));
+  MBL_HIP(hipMemcpyAsync(bw->scale2, bw->h_stage + R, sizeof(double) * R, hipMemcpyHostToDevice,
+                         s));
+  hipLaunchKernelGGL(k_baxpby, dim3(bflat_grid(n * R)), dim3(kWG), 0, s, n, R, bw->scale, x,
+                     bw->scale2, y);
+  MBL_HIP(hipGetLastError());
+  return MBL_OK;
+}
+
+static mbl_status bcgs_pass(mbl_batch_s* bw, int64_t n, int k, double* w, hipStream_t s) {
+  const int R = bw->R;
+  const int G = std::max<int>(1, std::min<int64_t>(256, (n + 255) / 256));
+  const int64_t vstride = n * R;
+  hipLaunchKernelGGL(k_bmultidot, dim3(G, (k + 3) / 4), dim3(kWG), 0, s, n, R, bw->V, vstride, k,
+                     w, bw->partials2);
+  MBL_HIP(hipGetLastError());
+  // coef[c * R + r] = sum_g partials[(g * k + c) * R + r]: per-realization reduce with k*R values
+  hipLaunchKernelGGL(k_breduce, dim3(k * R), dim3(kWG), 0, s, bw->partials2, G, k * R, 1,
+                     bw->coef);
+  MBL_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_bcgs_update, dim3(bflat_grid(n * R)), dim3(kWG), sizeof(double) * k * R, s,
+                     n, R, bw->V, vstride, k, bw->coef, w);
+  MBL_HIP(hipGetLastError());
+  return MBL_OK;
+}
+
+double gershgorin_bound(const mbl_basis_s* b, const double* h);
+
+// norms ||(H_r - shift_r) v_r|| for all r (fields uploaded with shifts)
+static mbl_status bapply_norms(mbl_basis_s* b, mbl_batch_s* bw, const double* v, double* out,
+                               hipStream_t s) {
+  BatchDev Q{bw->h, bw->c0, bw->R};
+  MBL_TRY((launch_bapply<double, 0, false>(b, Q, nullptr, v, bw->t64, nullptr, s)));
+  MBL_TRY(bdot_host(bw, b->n, bw->t64, bw->t64, out, s));
+  for (int r = 0; r < bw->R; ++r) out[r] = std::sqrt(out[r]);
+  return MBL_OK;
+}
+
+static mbl_status bsi_lanczos_run(mbl_basis_s* b, mbl_batch_s* bw, const double* h,
+                                  const double* sigma, int nev, int mmax, double minres_tol,
+                                  int64_t minres_kmax, double eig_tol, double gap_tol,
+                                  const double* escale_in, const double* v0, uint64_t seed,
+                                  int precision, int precond, double* evals, double* evecs,
+                                  double* resid, mbl_si_info* info, hipStream_t s) {
+  const auto t_start = std::chrono::steady_clock::now();
+  const int R = bw->R, L = b->L;
+  const int64_t n = b->n, NR = n * R;
+  std::vector<double> escale(R);
+  for (int r = 0; r < R; ++r)
+    escale[r] = (escale_in && escale_in[r] > 0) ? escale_in[r]
+                                                : gershgorin_bound(b, h + (size_t)r * L);
+  MBL_TRY(bupload(bw, h, sigma, s));
+  double* V = bw->V;
+  if (v0)
+    MBL_HIP(hipMemcpyAsync(V, v0, sizeof(double) * NR, hipMemcpyDeviceToDevice, s));
+  else
+    MBL_HIP(launch_splitmix(NR, seed, V, s));
+  std::vector<double> nv(R), ones(R, 1.0), zeros(R, 0.0);
+  MBL_TRY(bdot_host(bw, n, V, V, nv.data(), s));
+  std::vector<double> inv(R);
+  for (int r = 0; r < R; ++r) {
+    if (!(nv[r] > 0) || !std::isfinite(nv[r])) {
+      set_error("start vector has zero or non-finite norm");
+      return MBL_ERR_ARG;
+    }
+    inv[r] = 1.0 / std::sqrt(nv[r]);
+  }
+  MBL_TRY(baxpby(bw, n, inv, V, zeros, V, s));
+  std::vector<std::vector<double>> al(R), be(R), theta(R), Y(R);
+  std::vector<std::vector<int>> sel(R);
+  std::vector<int> active(R, 1), ksteps(R, 0);
+  std::vector<double> beta_k(R, 0.0);
+  int64_t total_iters = 0;
+  std::vector<int64_t> its;
+  std::vector<double> phis;
+  int k = 0;
+  std::vector<double> alpha(R), bb(R), nav(R);
+  for (k = 1; k <= mmax; ++k) {
+    double* vk = V + (size_t)(k - 1) * NR;
+    MBL_TRY(bupload(bw, h, sigma, s));
+    MBL_TRY(bminres_run(b, bw, precision, precond, vk, bw->x, minres_tol, minres_kmax, active, s,
+                        its, phis));
+    for (int r = 0; r < R; ++r) total_iters += its[r];
+    // w = x - beta_k v_{k-1}
+    MBL_HIP(hipMemcpyAsync(bw->w, bw->x, sizeof(double) * NR, hipMemcpyDeviceToDevice, s));
+    if (k > 1) {
+      std::vector<double> mb(R);
+      for (int r = 0; r < R; ++r) mb[r] = -beta_k[r];
+      MBL_TRY(baxpby(bw, n, mb, V + (size_t)(k - 2) * NR, ones, bw->w, s));
+    }
+    MBL_TRY(bdot_host(bw, n, vk, bw->w, alpha.data(), s));
+    {
+      std::vector<double> ma(R);
+      for (int r = 0; r < R; ++r) ma[r] = -alpha[r];
+      MBL_TRY(baxpby(bw, n, ma, vk, ones, bw->w, s));
+    }
+    MBL_TRY(bcgs_pass(bw, n, k, bw->w, s));
+    MBL_TRY(bcgs_pass(bw, n, k, bw->w, s));
+    MBL_TRY(bdot_host(bw, n, bw->w, bw->w, bb.data(), s));
+    std::vector<double> invb(R, 0.0);
+    for (int r = 0; r < R; ++r) {
+      if (!active[r]) continue;
+      const double bn = std::sqrt(bb[r]);
+      al[r].push_back(alpha[r]);
+      be[r].push_back(bn);
+      ksteps[r] = k;
+      if (!std::isfinite(alpha[r]) || !std::isfinite(bn)) {
+        set_error("non-finite Lanczos coefficient (batched)");
+        return MBL_ERR_NUMERIC;
+      }
+      theta[r].assign(k, 0.0);
+      Y[r].assign((size_t)k * k, 0.0);
+      if (tridiag_eig(k, al[r].data(), be[r].data(), theta[r].data(), Y[r].data()) != 0) {
+        set_error("tridiagonal eigensolver did not converge (batched)");
+        return MBL_ERR_NUMERIC;
+      }
+      double tmax = 0;
+      for (double t : theta[r]) tmax = std::max(tmax, std::fabs(t));
+      invb[r] = (bn > 1e-14 * tmax) ? 1.0 / bn : 0.0;
+      beta_k[r] = bn;
+    }
+    // v_{k+1} = w / beta_{k+1} (zero for realizations that stopped or broke down)
+    double* vn = V + (size_t)k * NR;
+    MBL_TRY(baxpby(bw, n, invb, bw->w, zeros, vn, s));
+    MBL_TRY(bapply_norms(b, bw, vn, nav.data(), s));
+    bool all_conv = true;
+    for (int r = 0; r < R; ++r) {
+      if (!active[r]) continue;
+      if (k < nev) {
+        all_conv = false;
+        continue;
+      }
+      const int kr = k;
+      std::vector<int> idx(kr);
+      std::iota(idx.begin(), idx.end(), 0);
+      std::stable_sort(idx.begin(), idx.end(), [&](int a, int c) {
+        return std::fabs(theta[r][a]) > std::fabs(theta[r][c]);
+      });
+      sel[r].assign(idx.begin(), idx.begin() + nev);
+      bool conv = true;
+      const bool broke = invb[r] == 0.0;
+      for (int i : sel[r]) {
+        const double est = broke ? 0.0
+                                 : std::fabs(be[r].back() * Y[r][(size_t)i * kr + (kr - 1)] /
+                                             theta[r][i]) * nav[r];
+        const double lam = sigma[r] + 1.0 / theta[r][i];
+        double gap = INFINITY;
+        for (int jj = 0; jj < kr; ++jj)
+          if (jj != i) gap = std::min(gap, std::fabs(sigma[r] + 1.0 / theta[r][jj] - lam));
+        bool ok = est <= eig_tol * escale[r];
+        if (gap_tol > 0) ok = ok && est <= gap_tol * gap;
+        conv = conv && ok;
+      }
+      if (conv || broke) active[r] = 0;
+      else all_conv = false;
+    }
+    if (all_conv) break;
+  }
+  if (k > mmax) k = mmax;
+  const int kmaxr = *std::max_element(ksteps.begin(), ksteps.end());
+  // Ritz vectors: U_t[:, r] = V[:, :k_r, r] Y_r[:, sel_t]; Y padded to kmaxr rows
+  std::vector<double> Ys((size_t)R * kmaxr * nev, 0.0);
+  std::vector<double> lam((size_t)R * nev);
+  for (int r = 0; r < R; ++r) {
+    const int kr = ksteps[r];
+    if ((int)sel[r].size() < nev) {
+      set_error("Krylov space became invariant before nev steps (batched)");
+      return MBL_ERR_NUMERIC;
+    }
+    std::sort(sel[r].begin(), sel[r].end(), [&](int a, int c) {
+      return sigma[r] + 1.0 / theta[r][a] < sigma[r] + 1.0 / theta[r][c];
+    });
+    for (int t = 0; t < nev; ++t) {
+      lam[(size_t)r * nev + t] = sigma[r] + 1.0 / theta[r][sel[r][t]];
+      for (int c = 0; c < kr; ++c)
+        Ys[((size_t)r * kmaxr + c) * nev + t] = Y[r][(size_t)sel[r][t] * kr + c];
+    }
+  }
+  MBL_HIP(hipMemcpyAsync(bw->ycoef, Ys.data(), sizeof(double) * Ys.size(), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_britz, dim3(bflat_grid(NR), nev), dim3(kWG), 0, s, n, R, V, NR, kmaxr,
+                     bw->ycoef, nev, evecs, NR);
+  MBL_HIP(hipGetLastError());
+  // normalise and explicit residuals ||H_r u - lambda u||
+  std::vector<double> nn(R), invn(R), lt(R);
+  for (int t = 0; t < nev; ++t) {
+    double* u = evecs + (size_t)t * NR;
+    MBL_TRY(bdot_host(bw, n, u, u, nn.data(), s));
+    for (int r = 0; r < R; ++r) invn[r] = 1.0 / std::sqrt(nn[r]);
+    MBL_TRY(baxpby(bw, n, invn, u, zeros, u, s));
+    for (int r = 0; r < R; ++r) lt[r] = lam[(size_t)r * nev + t];
+    MBL_TRY(bupload(bw, h, lt.data(), s));
+    std::vector<double> rn(R);
+    MBL_TRY(bapply_norms(b, bw, u, rn.data(), s));
+    for (int r = 0; r < R; ++r) {
+      evals[(size_t)r * nev + t] = lam[(size_t)r * nev + t];
+      if (resid) resid[(size_t)r * nev + t] = rn[r];
+    }
+  }
+  MBL_HIP(hipStreamSynchronize(s));
+  const double secs =
+      std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  int all_ok = 1;
+  for (int r = 0; r < R; ++r) {
+    int nconv = 0;
+    double mx = 0;
+    for (int t = 0; t < nev; ++t) {
+      const double rr = resid ? resid[(size_t)r * nev + t] : 0.0;
+      mx = std::max(mx, rr / escale[r]);
+      if (rr <= eig_tol * escale[r]) ++nconv;
+    }
+    if (nconv < nev) all_ok = 0;
+    if (info) {
+      info[r].steps = ksteps[r];
+      info[r].nconv = nconv;
+      info[r].minres_iters = 0;
+      info[r].max_rel_resid = mx;
+      info[r].seconds = secs;
+    }
+  }
+  if (info) info[0].minres_iters = total_iters;
+  if (!all_ok) {
+    set_error("some batched eigenpairs did not converge");
+    return MBL_WARN_NOCONV;
+  }
+  return MBL_OK;
+}
+
+static void free_batch(mbl_batch_s* w) {
+  if (!w) return;
+  double* bufs[] = {w->h, w->c0, w->z[0], w->z[1], w->q[0], w->q[1], w->d[0], w->d[1], w->p,
+                    w->e, w->r64, w->t64, w->w, w->x, w->V, w->coef, w->ycoef, w->partials1,
+                    w->partials2, w->red, w->scale, w->scale2};
+  for (double* p : bufs) (void)hipFree(p);
+  (void)hipFree(w->S);
+  if (w->h_state) hipHostFree(w->h_state);
+  if (w->h_red) hipHostFree(w->h_red);
+  if (w->h_stage) hipHostFree(w->h_stage);
+  for (int i = 0; i < 2; ++i)
+    if (w->ev[i]) hipEventDestroy(w->ev[i]);
+  delete w;
+}
+
+static mbl_status create_batch(mbl_basis_s* b, int R, int mmax, int nevmax, mbl_batch_s** out) {
+  mbl_batch_s* w = new (std::nothrow) mbl_batch_s();
+  if (!w) {
+    set_error("host allocation failed");
+    return MBL_ERR_NOMEM;
+  }
+  w->basis = b;
+  w->R = R;
+  w->mmax = mmax;
+  w->nevmax = nevmax;
+  w->n = b->n;
+  const size_t NR = (size_t)b->n * R;
+  mbl_status st = MBL_OK;
+  auto A = [&](double** p, size_t cnt) {
+    if (st != MBL_OK) return;
+    if (hipMalloc((void**)p, std::max<size_t>(cnt, 1) * sizeof(double)) != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("device allocation failed (batched workspace)");
+      st = MBL_ERR_NOMEM;
+      return;
+    }
+    w->bytes += (int64_t)(cnt * sizeof(double));
+  };
+  A(&w->h, (size_t)R * b->L);
+  A(&w->c0, R);
+  for (int i = 0; i < 2; ++i) {
+    A(&w->z[i], NR);
+    A(&w->q[i], NR);
+    A(&w->d[i], NR);
+  }
+  A(&w->p, NR);
+  A(&w->e, NR);
+  A(&w->r64, NR);
+  A(&w->t64, NR);
+  A(&w->w, NR);
+  A(&w->x, NR);
+  if (mmax > 0) A(&w->V, NR * (size_t)(mmax + 1));
+  A(&w->coef, (size_t)(mmax + 1) * R);
+  A(&w->ycoef, (size_t)R * (mmax + 1) * std::max(nevmax, 1));
+  w->part_elems = std::max<size_t>((size_t)kBGrid * R * 2, (size_t)256 * (mmax + 1) * R);
+  A(&w->partials1, w->part_elems);
+  A(&w->partials2, w->part_elems);
+  A(&w->red, (size_t)std::max(R * 64, (mmax + 1) * R));
+  A(&w->scale, R);
+  A(&w->scale2, R);
+  if (st == MBL_OK && hipMalloc((void**)&w->S, sizeof(BState) * 2 * R) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("device allocation failed (batched state)");
+    st = MBL_ERR_NOMEM;
+  }
+  if (st == MBL_OK &&
+      (hipHostMalloc((void**)&w->h_state, sizeof(BState) * 4 * R) != hipSuccess ||
+       hipHostMalloc((void**)&w->h_red, sizeof(double) * std::max(R * 64, (mmax + 1) * R)) !=
+           hipSuccess ||
+       hipHostMalloc((void**)&w->h_stage, sizeof(double) * ((size_t)R * (b->L + 1) + 4 * R)) !=
+           hipSuccess)) {
+    (void)hipGetLastError();
+    set_error("pinned host allocation failed (batched)");
+    st = MBL_ERR_NOMEM;
+  }
+  for (int i = 0; i < 2 && st == MBL_OK; ++i)
+    if (hipEventCreateWithFlags(&w->ev[i], hipEventDisableTiming) != hipSuccess) {
+      set_error("hipEventCreate failed");
+      st = MBL_ERR_HIP;
+    }
+  if (st != MBL_OK) {
+    free_batch(w);
+    return st;
+  }
+  *out = w;
+  return MBL_OK;
+}
+
+static bool pow2(int R) { return R >= 2 && R <= kBMaxR && (R & (R - 1)) == 0; }
+
+}  // namespace mbl
+
+using namespace mbl;
+
+extern "C" {
+
+mbl_status mbl_batch_create(mbl_basis b, int R, int mmax, int nevmax, mbl_batch* out) {
+  clear_error();
+  MBL_ARG(b && out, "NULL argument");
+  MBL_ARG(pow2(R), "R must be a power of two in [2, 32]");
+  MBL_ARG(mmax >= 0 && mmax <= kMaxLanczos && nevmax >= 0 && nevmax <= std::max(mmax, 1),
+          "need 0 <= nevmax <= mmax <= 1000");
+  MBL_ARG(batched_split_supported(b), "batched form needs the library's default lo_bits for L");
+  MBL_ARG(blds_bytes(R, b->L, b->nlo) <= 65536, "R too large for this L (LDS)");
+  return create_batch(b, R, mmax, nevmax, out);
+}
+
+void mbl_batch_free(mbl_batch w) { free_batch(w); }
+
+mbl_status mbl_batch_bytes(mbl_batch w, int64_t* bytes) {
+  clear_error();
+  MBL_ARG(w && bytes, "NULL argument");
+  *bytes = w->bytes;
+  return MBL_OK;
+}
+
+mbl_status mbl_apply_H_batched(mbl_basis b, mbl_batch w, const double* h_host,
+                               const double* sigma_host, const double* x_dev, double* y_dev,
+                               void* stream) {
+  clear_error();
+  MBL_ARG(b && w && h_host && sigma_host && x_dev && y_dev, "NULL argument");
+  MBL_ARG(w->basis == b, "batch workspace belongs to another basis");
+  MBL_ARG(x_dev != y_dev, "x and y must not alias");
+  for (int r = 0; r < w->R; ++r)
+    MBL_ARG(fields_finite(b->L, h_host + (size_t)r * b->L) && std::isfinite(sigma_host[r]),
+            "non-finite h or sigma");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  MBL_TRY(bupload(w, h_host, sigma_host, s));
+  BatchDev Q{w->h, w->c0, w->R};
+  return launch_bapply<double, 0, false>(b, Q, nullptr, x_dev, y_dev, nullptr, s);
+}
+
+mbl_status mbl_apply_H_batched_f32(mbl_basis b, mbl_batch w, const double* h_host,
+                                   const double* sigma_host, const float* x_dev, float* y_dev,
+                                   void* stream) {
+  clear_error();
+  MBL_ARG(b && w && h_host && sigma_host && x_dev && y_dev, "NULL argument");
+  MBL_ARG(w->basis == b, "batch workspace belongs to another basis");
+  MBL_ARG((const void*)x_dev != (const void*)y_dev, "x and y must not alias");
+  for (int r = 0; r < w->R; ++r)
+    MBL_ARG(fields_finite(b->L, h_host + (size_t)r * b->L) && std::isfinite(sigma_host[r]),
+            "non-finite h or sigma");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  MBL_TRY(bupload(w, h_host, sigma_host, s));
+  BatchDev Q{w->h, w->c0, w->R};
+  return launch_bapply<float, 0, false>(b, Q, nullptr, x_dev, y_dev, nullptr, s);
+}
+
+mbl_status mbl_minres_solve_batched(mbl_basis b, mbl_batch w, const double* h_host,
+                                    const double* sigma_host, const double* rhs_dev,
+                                    double* x_dev, double tol, int64_t kmax, int precision,
+                                    int precond, int64_t* iters_host, double* phi_host,
+                                    void* stream) {
+  clear_error();
+  MBL_ARG(b && w && h_host && sigma_host && rhs_dev && x_dev, "NULL argument");
+  MBL_ARG(w->basis == b, "batch workspace belongs to another basis");
+  MBL_ARG(rhs_dev != x_dev, "rhs and x must not alias");
+  MBL_ARG(tol > 0 && kmax >= 1, "bad tol or kmax");
+  MBL_ARG(precision == MBL_FP64 || precision == MBL_FP32_INNER, "unknown precision");
+  MBL_ARG(precond >= 0 && precond <= 2, "unknown preconditioner");
+  for (int r = 0; r < w->R; ++r)
+    MBL_ARG(fields_finite(b->L, h_host + (size_t)r * b->L) && std::isfinite(sigma_host[r]),
+            "non-finite h or sigma");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  MBL_TRY(bupload(w, h_host, sigma_host, s));
+  std::vector<int> active(w->R, 1);
+  std::vector<int64_t> its;
+  std::vector<double> phi;
+  MBL_TRY(bminres_run(b, w, precision, precond, rhs_dev, x_dev, tol, kmax, active, s, its, phi));
+  MBL_HIP(hipStreamSynchronize(s));
+  bool all = true;
+  for (int r = 0; r < w->R; ++r) {
+    if (iters_host) iters_host[r] = its[r];
+    if (phi_host) phi_host[r] = phi[r];
+    all = all && phi[r] < tol;
+  }
+  return all ? MBL_OK : MBL_WARN_NOCONV;
+}
+
+mbl_status mbl_si_lanczos_batched(mbl_basis b, mbl_batch w, const double* h_host,
+                                  const double* sigma_host, int nev, int mmax, double minres_tol,
+                                  int64_t minres_kmax, double eig_tol, double gap_tol,
+                                  const double* escale_host, const double* v0_dev, uint64_t seed,
+                                  int precision, int precond, double* evals_host,
+                                  double* evecs_dev, double* resid_host, mbl_si_info* info_host,
+                                  void* stream) {
+  clear_error();
+  MBL_ARG(b && w && h_host && sigma_host && evals_host && evecs_dev, "NULL argument");
+  MBL_ARG(w->basis == b, "batch workspace belongs to another basis");
+  MBL_ARG(nev >= 1 && nev <= w->nevmax, "need 1 <= nev <= nevmax of the batch workspace");
+  MBL_ARG(mmax >= nev && mmax <= w->mmax && mmax <= b->n, "need nev <= mmax <= workspace mmax");
+  MBL_ARG(minres_tol > 0 && minres_kmax >= 1 && eig_tol > 0, "bad tolerances");
+  MBL_ARG(precision == MBL_FP64 || precision == MBL_FP32_INNER, "unknown precision");
+  MBL_ARG(precond >= 0 && precond <= 2, "unknown preconditioner");
+  for (int r = 0; r < w->R; ++r)
+    MBL_ARG(fields_finite(b->L, h_host + (size_t)r * b->L) && std::isfinite(sigma_host[r]),
+            "non-finite h or sigma");
+  return bsi_lanczos_run(b, w, h_host, sigma_host, nev, mmax, minres_tol, minres_kmax, eig_tol,
+                         gap_tol, escale_host, v0_dev, seed, precision, precond, evals_host,
+                         evecs_dev, resid_host, info_host, reinterpret_cast<hipStream_t>(stream));
+}
+
+mbl_status mbl_twist_expect_batched(mbl_basis b, mbl_batch w, const double* psi_dev, int nvec,
+                                    double* z_host, void* stream) {
+  clear_error();
+  MBL_ARG(b && w && psi_dev && z_host, "NULL argument");
+  MBL_ARG(w->basis == b, "batch workspace belongs to another basis");
+  MBL_ARG(nvec >= 1, "nvec must be >= 1");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int R = w->R, L = b->L;
+  const int G = bgrid(b);
+  MBL_ARG((size_t)G * R * 2 <= w->part_elems, "internal: partials too small");
+  BTwistTab T{};
+  const double pi = 3.14159265358979323846;
+  for (int m = 0; m < 2 * L; ++m) {
+    T.c[m] = std::cos(pi * m / L);
+    T.s[m] = std::sin(pi * m / L);
+  }
+  BatchDev Q{w->h, w->c0, R};
+  const size_t lds = blds_bytes(R, L, b->nlo);
+  const int64_t NR = b->n * R;
+  for (int t = 0; t < nvec; ++t) {
+    const DevBasis B = b->dev();
+#define MBL_CASE(LL, NN)                                                                      \
+  case LL * 64 + NN:                                                                         \
+    hipLaunchKernelGGL((k_btwist<LL>), dim3(G, 1), dim3(kBWG), lds, s, B, Q, T,              \
+                       psi_dev + (size_t)t * NR, NR, w->partials1);                          \
+    break;
+    MBL_BDISPATCH(MBL_CASE)
+#undef MBL_CASE
+    MBL_HIP(hipGetLastError());
+    std::vector<double> out(2 * R);
+    MBL_TRY(breduce_host(w, w->partials1, G, 2, out.data(), s));
+    for (int r = 0; r < R; ++r) {
+      z_host[((size_t)r * nvec + t) * 2] = out[2 * r];
+      z_host[((size_t)r * nvec + t) * 2 + 1] = out[2 * r + 1];
+    }
+  }
+  return MBL_OK;
+}
+
+}  // extern "C"

@@ -19,150 +19,29 @@
 //
 // Reductions are per-workgroup partial sums written in a fixed order and
 // reduced again in a fixed order, so results are bitwise reproducible.
-#include "mbl_internal.h"
+#include "rows.h"
 
 namespace mbl {
 
 // ---------------------------------------------------------------------------
-// small device helpers
-
-__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-// Sum over the workgroup; the result is returned to every thread. red must
-// hold one double per wave. Fixed order: lanes by butterfly, then waves 0..3.
-__device__ __forceinline__ double block_sum_all(double v, double* red) {
-  v = wave_sum(v);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double s = 0.0;
-#pragma unroll
-  for (int w = 0; w < kWavesPerWG; ++w) s += red[w];
-  return s;
-}
-
-struct RowTables {
-  const double* lut;       // nibble field table, 16 entries per nibble
-  double* red;             // reduction scratch
-  const uint16_t* rank;    // lo_rank in LDS
-  const uint16_t* state;   // lo_state in LDS
-};
-
-constexpr int kLdsLut = 128;   // doubles (8 nibbles x 16)
-constexpr int kLdsRed = 8;     // doubles
-
-__device__ __forceinline__ RowTables setup_tables(const DevBasis& B, const FieldArgs& F,
-                                                  unsigned char* smem) {
-  double* lut = reinterpret_cast<double*>(smem);
-  double* red = lut + kLdsLut;
-  uint16_t* rank = reinterpret_cast<uint16_t*>(red + kLdsRed);
-  uint16_t* state = rank + (1u << B.nlo);
-  const int nnib = (B.L + 3) >> 2;
-  for (int t = threadIdx.x; t < nnib * 16; t += blockDim.x) {
-    const int k = t >> 4, v = t & 15;
-    double acc = 0.0;
-    for (int b = 0; b < 4; ++b) {
-      const int site = 4 * k + b;
-      if (site < B.L && ((v >> b) & 1)) acc += F.h[site];
-    }
-    lut[t] = acc;
-  }
-  const int words = (1 << B.nlo) >> 1;   // two uint16 per word, nlo >= 1
-  const uint32_t* gr = reinterpret_cast<const uint32_t*>(B.lo_rank);
-  const uint32_t* gs = reinterpret_cast<const uint32_t*>(B.lo_state);
-  uint32_t* sr = reinterpret_cast<uint32_t*>(rank);
-  uint32_t* ss = reinterpret_cast<uint32_t*>(state);
-  for (int t = threadIdx.x; t < words; t += blockDim.x) {
-    sr[t] = gr[t];
-    ss[t] = gs[t];
-  }
-  return RowTables{lut, red, rank, state};
-}
-
-// a_aa - sigma and the number of antiparallel bonds of state a.
-__device__ __forceinline__ double row_diag(const DevBasis& B, const FieldArgs& F,
-                                           const RowTables& t, uint32_t a, int& nanti) {
-  const uint32_t mask = (B.L == 32) ? 0xffffffffu : ((1u << B.L) - 1u);
-  const uint32_t rot = ((a << 1) | (a >> (B.L - 1))) & mask;
-  nanti = __popc(a ^ rot);
-  const int nnib = (B.L + 3) >> 2;
-  double f = 0.0;
-  for (int k = 0; k < nnib; ++k) f += t.lut[(k << 4) + ((a >> (4 * k)) & 15u)];
-  return F.c0 - 0.5 * (double)nanti - f;
-}
-
-// sum of x over the states reached by one spin swap on an antiparallel bond
-template <typename T>
-__device__ __forceinline__ double row_offdiag(const DevBasis& B, const RowTables& t,
-                                              const T* __restrict__ x, uint32_t hi, uint32_t lo,
-                                              uint32_t j, uint32_t block0) {
-  const int nlo = B.nlo, nhi = B.nhi;
-  const T* xb = x + block0;
-  double off = 0.0;
-  // bonds inside the low bits: same block, target from the LDS rank table
-  for (int b = 0; b + 1 < nlo; ++b) {
-    if (((lo >> b) ^ (lo >> (b + 1))) & 1u) off += (double)xb[t.rank[lo ^ (3u << b)]];
-  }
-  // bond between bit nlo-1 and bit nlo
-  {
-    const uint32_t hb = uni(B.hi_off[hi ^ 1u]);
-    if (((lo >> (nlo - 1)) ^ hi) & 1u)
-      off += (double)x[(size_t)hb + t.rank[lo ^ (1u << (nlo - 1))]];
-  }
-  // bonds inside the high bits: uniform over the wave, contiguous loads
-  for (int b = 0; b + 1 < nhi; ++b) {
-    if (((hi >> b) ^ (hi >> (b + 1))) & 1u) {
-      const uint32_t hb = uni(B.hi_off[hi ^ (3u << b)]);
-      off += (double)x[(size_t)hb + j];
-    }
-  }
-  // periodic bond between bit L-1 and bit 0
-  {
-    const uint32_t hb = uni(B.hi_off[hi ^ (1u << (nhi - 1))]);
-    if (((hi >> (nhi - 1)) ^ lo) & 1u) off += (double)x[(size_t)hb + t.rank[lo ^ 1u]];
-  }
-  return off;
-}
-
-// Iterate this wave's chunks; body(row, hi, lo, j, block0, a) for valid lanes.
-template <typename Body>
-__device__ __forceinline__ void for_rows(const DevBasis& B, const RowTables& t, Body body) {
-  const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t wave = uni(threadIdx.x >> 6);
-  const uint32_t stride = gridDim.x * kWavesPerWG;
-  for (uint32_t c = blockIdx.x * kWavesPerWG + wave; c < (uint32_t)B.nchunks; c += stride) {
-    const uint4 ch = B.chunks[c];
-    const uint32_t hi = uni(ch.x), j0 = uni(ch.y), cnt = uni(ch.z), row0 = uni(ch.w);
-    const uint32_t coff = uni(B.lo_coff[B.half - __popc(hi)]);
-    if (lane < cnt) {
-      const uint32_t j = j0 + lane;
-      const uint32_t lo = t.state[coff + j];
-      body(row0 + lane, hi, lo, j, row0 - j0, (hi << B.nlo) | lo);
-    }
-  }
-}
-
-// ---------------------------------------------------------------------------
-// y = (H - sigma) x. MODE 0: plain; 1: partial sums of x.y; 2: partial sums of y.y.
-template <typename T, int MODE>
-__global__ __launch_bounds__(kWG) void k_apply(DevBasis B, FieldArgs F, const T* __restrict__ x,
-                                               T* __restrict__ y, double* __restrict__ partials) {
+// y = (H - sigma) x. MODE 0: plain; 1: partial sums of x.y; 2: partial sums of
+// y.y. GUARD: return at once when the MINRES state S is done. (L, NLO) = (0, 0)
+// is the runtime-split form.
+template <typename T, int MODE, bool GUARD, int L, int NLO>
+__global__ __launch_bounds__(kWG) void k_apply(DevBasis B, FieldArgs F, const MinresState* S,
+                                               const T* __restrict__ x, T* __restrict__ y,
+                                               double* __restrict__ partials) {
+  if (GUARD && S->done) return;
   extern __shared__ __align__(16) unsigned char smem[];
-  const RowTables t = setup_tables(B, F, smem);
+  const RowTables t = setup_tables<L>(B, F, smem);
   __syncthreads();
   double acc = 0.0;
   for_rows(B, t, [&](uint32_t row, uint32_t hi, uint32_t lo, uint32_t j, uint32_t block0,
                      uint32_t a) {
-    int na;
-    const double dsh = row_diag(B, F, t, a, na);
     const double xi = (double)x[row];
-    const double off = row_offdiag<T>(B, t, x, hi, lo, j, block0);
+    const double off = RowOps<T, L, NLO>::offdiag(B, t, x, hi, lo, j, block0);
+    int na;
+    const double dsh = row_diag<L>(B, F, t, a, na);
     const T yt = (T)(dsh * xi + 0.5 * off);
     y[row] = yt;
     if (MODE == 1) acc += xi * (double)yt;
@@ -174,38 +53,6 @@ __global__ __launch_bounds__(kWG) void k_apply(DevBasis B, FieldArgs F, const T*
   }
 }
 
-// p = A q with partial sums of q . p, skipped once the MINRES state is done
-template <typename T>
-__global__ __launch_bounds__(kWG) void k_apply_guarded(DevBasis B, FieldArgs F,
-                                                       const MinresState* __restrict__ S,
-                                                       const T* __restrict__ x, T* __restrict__ y,
-                                                       double* __restrict__ partials) {
-  if (S->done) return;
-  extern __shared__ __align__(16) unsigned char smem[];
-  const RowTables t = setup_tables(B, F, smem);
-  __syncthreads();
-  double acc = 0.0;
-  for_rows(B, t, [&](uint32_t row, uint32_t hi, uint32_t lo, uint32_t j, uint32_t block0,
-                     uint32_t a) {
-    int na;
-    const double dsh = row_diag(B, F, t, a, na);
-    const double xi = (double)x[row];
-    const double off = row_offdiag<T>(B, t, x, hi, lo, j, block0);
-    const T yt = (T)(dsh * xi + 0.5 * off);
-    y[row] = yt;
-    acc += xi * (double)yt;
-  });
-  const double s = block_sum_all(acc, t.red);
-  if (threadIdx.x == 0) partials[blockIdx.x] = s;
-}
-
-// preconditioner value m_i for row kind (Sec. II)
-__device__ __forceinline__ double precond_value(int kind, double dsh, int nanti) {
-  if (kind == MBL_PRECOND_ROW) return sqrt(dsh * dsh + 0.25 * (double)nanti);
-  if (kind == MBL_PRECOND_JACOBI) return fabs(dsh);
-  return 1.0;
-}
-
 __global__ __launch_bounds__(kWG) void k_precond(DevBasis B, FieldArgs F, int kind,
                                                  const double* z, double* q) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -213,26 +60,27 @@ __global__ __launch_bounds__(kWG) void k_precond(DevBasis B, FieldArgs F, int ki
   __syncthreads();
   for_rows(B, t, [&](uint32_t row, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t a) {
     int na;
-    const double dsh = row_diag(B, F, t, a, na);
+    const double dsh = row_diag<0>(B, F, t, a, na);
     q[row] = z[row] / precond_value(kind, dsh, na);
   });
 }
 
 // r = rhs - (H - sigma) x, partials[2g] = sum r^2 / m, partials[2g+1] = sum r^2
+template <int L, int NLO>
 __global__ __launch_bounds__(kWG) void k_residual(DevBasis B, FieldArgs F, int kind,
                                                   const double* __restrict__ rhs,
                                                   const double* __restrict__ x,
                                                   double* __restrict__ r,
                                                   double* __restrict__ partials) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const RowTables t = setup_tables(B, F, smem);
+  const RowTables t = setup_tables<L>(B, F, smem);
   __syncthreads();
   double am = 0.0, a2 = 0.0;
   for_rows(B, t, [&](uint32_t row, uint32_t hi, uint32_t lo, uint32_t j, uint32_t block0,
                      uint32_t a) {
+    const double off = RowOps<double, L, NLO>::offdiag(B, t, x, hi, lo, j, block0);
     int na;
-    const double dsh = row_diag(B, F, t, a, na);
-    const double off = row_offdiag<double>(B, t, x, hi, lo, j, block0);
+    const double dsh = row_diag<L>(B, F, t, a, na);
     const double ri = rhs[row] - (dsh * x[row] + 0.5 * off);
     r[row] = ri;
     am += ri * ri / precond_value(kind, dsh, na);
@@ -379,31 +227,45 @@ int row_grid(const mbl_basis_s* b) {
   int g = (b->nchunks + kWavesPerWG - 1) / kWavesPerWG;
   if (g > kMaxPartials) g = kMaxPartials;
   if (g < 1) g = 1;
-  return g;
+  return g >= 64 ? (g / 8) * 8 : g;   // whole XCD slices once the grid is large
 }
 
-size_t row_lds_bytes(const mbl_basis_s* b) {
-  return (kLdsLut + kLdsRed) * sizeof(double) + 2 * sizeof(uint16_t) * ((size_t)1 << b->nlo);
-}
+size_t row_lds_bytes(const mbl_basis_s* b) { return row_lds_for(b->nlo); }
 
 static int dense_grid(int64_t n) {
   int64_t g = (n + kWG - 1) / kWG;
   return (int)(g < 1 ? 1 : (g > kDenseGrid ? kDenseGrid : g));
 }
 
+// launch the (L, NLO) instance matching the basis, else the runtime form
+template <typename T, int MODE, bool GUARD>
+static hipError_t apply_dispatch(const mbl_basis_s* b, const FieldArgs& F, const MinresState* S,
+                                 const T* x, T* y, double* partials, hipStream_t s) {
+  const dim3 g(row_grid(b)), blk(kWG);
+  const size_t lds = row_lds_bytes(b);
+  const DevBasis B = b->dev();
+  switch (b->L * 64 + b->nlo) {
+#define MBL_CASE(LL, NN)                                                                     \
+  case LL * 64 + NN:                                                                        \
+    hipLaunchKernelGGL((k_apply<T, MODE, GUARD, LL, NN>), g, blk, lds, s, B, F, S, x, y,  \
+                       partials);                                                           \
+    return hipGetLastError();
+    MBL_FAST_SPLITS(MBL_CASE)
+#undef MBL_CASE
+    default:
+      hipLaunchKernelGGL((k_apply<T, MODE, GUARD, 0, 0>), g, blk, lds, s, B, F, S, x, y,
+                         partials);
+      return hipGetLastError();
+  }
+}
+
 template <typename T>
 hipError_t launch_apply(const mbl_basis_s* b, const FieldArgs& F, const T* x, T* y, int mode,
                         double* partials, int* nparts, hipStream_t s) {
-  const int g = row_grid(b);
-  const size_t lds = row_lds_bytes(b);
-  if (nparts) *nparts = g;
-  if (mode == 0)
-    hipLaunchKernelGGL((k_apply<T, 0>), dim3(g), dim3(kWG), lds, s, b->dev(), F, x, y, partials);
-  else if (mode == 1)
-    hipLaunchKernelGGL((k_apply<T, 1>), dim3(g), dim3(kWG), lds, s, b->dev(), F, x, y, partials);
-  else
-    hipLaunchKernelGGL((k_apply<T, 2>), dim3(g), dim3(kWG), lds, s, b->dev(), F, x, y, partials);
-  return hipGetLastError();
+  if (nparts) *nparts = row_grid(b);
+  if (mode == 0) return apply_dispatch<T, 0, false>(b, F, nullptr, x, y, partials, s);
+  if (mode == 1) return apply_dispatch<T, 1, false>(b, F, nullptr, x, y, partials, s);
+  return apply_dispatch<T, 2, false>(b, F, nullptr, x, y, partials, s);
 }
 template hipError_t launch_apply<double>(const mbl_basis_s*, const FieldArgs&, const double*,
                                          double*, int, double*, int*, hipStream_t);
@@ -413,9 +275,7 @@ template hipError_t launch_apply<float>(const mbl_basis_s*, const FieldArgs&, co
 template <typename T>
 hipError_t launch_minres_apply(const mbl_basis_s* b, const FieldArgs& F, const MinresState* S,
                                const T* q, T* p, double* partials, hipStream_t s) {
-  hipLaunchKernelGGL((k_apply_guarded<T>), dim3(row_grid(b)), dim3(kWG), row_lds_bytes(b), s,
-                     b->dev(), F, S, q, p, partials);
-  return hipGetLastError();
+  return apply_dispatch<T, 1, true>(b, F, S, q, p, partials, s);
 }
 template hipError_t launch_minres_apply<double>(const mbl_basis_s*, const FieldArgs&,
                                                 const MinresState*, const double*, double*,
@@ -436,9 +296,20 @@ hipError_t launch_residual(const mbl_basis_s* b, const FieldArgs& F, int precond
                            int* nparts, hipStream_t s) {
   const int g = row_grid(b);
   if (nparts) *nparts = g;
-  hipLaunchKernelGGL(k_residual, dim3(g), dim3(kWG), row_lds_bytes(b), s, b->dev(), F, precond,
-                     rhs, x, r, partials);
-  return hipGetLastError();
+  const size_t lds = row_lds_bytes(b);
+  switch (b->L * 64 + b->nlo) {
+#define MBL_CASE(LL, NN)                                                                    \
+  case LL * 64 + NN:                                                                       \
+    hipLaunchKernelGGL((k_residual<LL, NN>), dim3(g), dim3(kWG), lds, s, b->dev(), F,     \
+                       precond, rhs, x, r, partials);                                      \
+    return hipGetLastError();
+    MBL_FAST_SPLITS(MBL_CASE)
+#undef MBL_CASE
+    default:
+      hipLaunchKernelGGL((k_residual<0, 0>), dim3(g), dim3(kWG), lds, s, b->dev(), F, precond,
+                         rhs, x, r, partials);
+      return hipGetLastError();
+  }
 }
 
 hipError_t launch_states(const mbl_basis_s* b, uint32_t* states, hipStream_t s) {

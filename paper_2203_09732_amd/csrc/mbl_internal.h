@@ -124,6 +124,7 @@ struct mbl_workspace_s {
   double* partials2 = nullptr;   // kMaxPartials * 64
   double* red_out = nullptr;     // 256 doubles
   mbl::MinresState* state = nullptr;  // 2 slots
+  unsigned int* sync = nullptr;       // grid barrier counter + failure flag
   mbl::MinresState* h_state = nullptr;  // pinned host, 4 slots
   double* h_red = nullptr;              // pinned host, 256 doubles
   hipEvent_t ev[2] = {nullptr, nullptr};

@@ -17,98 +17,14 @@
 // Vector slots: z_{k-1}/z_{k+1} share a buffer (updated in place), so do
 // d_{k-2}/d_k; q_k and q_{k+1} alternate. With p and x that is 8 n-vectors
 // besides b.
-#include "mbl_internal.h"
+#include "rows.h"
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
+#include <string>
 
 namespace mbl {
-
-__device__ __forceinline__ uint32_t uni_m(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
-
-__device__ __forceinline__ double wave_sum_m(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-__device__ __forceinline__ double block_sum_m(double v, double* red) {
-  v = wave_sum_m(v);
-  __syncthreads();
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double s = 0.0;
-#pragma unroll
-  for (int w = 0; w < kWavesPerWG; ++w) s += red[w];
-  return s;
-}
-
-// every workgroup: identical fixed-order sum of P partials
-__device__ __forceinline__ double reduce_partials(const double* __restrict__ p, int P,
-                                                  double* red) {
-  double v = 0.0;
-  for (int i = threadIdx.x; i < P; i += blockDim.x) v += p[i];
-  return block_sum_m(v, red);
-}
-
-// ---- row machinery (same decomposition as the apply kernel) --------------
-struct MTables {
-  const double* lut;
-  double* red;
-  const uint16_t* state;
-};
-
-__device__ __forceinline__ MTables msetup(const DevBasis& B, const FieldArgs& F,
-                                          unsigned char* smem) {
-  double* lut = reinterpret_cast<double*>(smem);
-  double* red = lut + 128;
-  uint16_t* state = reinterpret_cast<uint16_t*>(red + 8);
-  const int nnib = (B.L + 3) >> 2;
-  for (int t = threadIdx.x; t < nnib * 16; t += blockDim.x) {
-    const int k = t >> 4, v = t & 15;
-    double acc = 0.0;
-    for (int b = 0; b < 4; ++b) {
-      const int site = 4 * k + b;
-      if (site < B.L && ((v >> b) & 1)) acc += F.h[site];
-    }
-    lut[t] = acc;
-  }
-  const int words = (1 << B.nlo) >> 1;
-  const uint32_t* gs = reinterpret_cast<const uint32_t*>(B.lo_state);
-  uint32_t* ss = reinterpret_cast<uint32_t*>(state);
-  for (int t = threadIdx.x; t < words; t += blockDim.x) ss[t] = gs[t];
-  return MTables{lut, red, state};
-}
-
-__device__ __forceinline__ double mprecond(const DevBasis& B, const FieldArgs& F,
-                                           const MTables& t, int kind, uint32_t a) {
-  if (kind == MBL_PRECOND_ID) return 1.0;
-  const uint32_t mask = (B.L == 32) ? 0xffffffffu : ((1u << B.L) - 1u);
-  const uint32_t rot = ((a << 1) | (a >> (B.L - 1))) & mask;
-  const int nanti = __popc(a ^ rot);
-  const int nnib = (B.L + 3) >> 2;
-  double f = 0.0;
-  for (int k = 0; k < nnib; ++k) f += t.lut[(k << 4) + ((a >> (4 * k)) & 15u)];
-  const double dsh = F.c0 - 0.5 * (double)nanti - f;
-  if (kind == MBL_PRECOND_ROW) return sqrt(dsh * dsh + 0.25 * (double)nanti);
-  return fabs(dsh);
-}
-
-template <typename Body>
-__device__ __forceinline__ void mfor_rows(const DevBasis& B, const MTables& t, Body body) {
-  const uint32_t lane = threadIdx.x & 63u;
-  const uint32_t wave = uni_m(threadIdx.x >> 6);
-  const uint32_t stride = gridDim.x * kWavesPerWG;
-  for (uint32_t c = blockIdx.x * kWavesPerWG + wave; c < (uint32_t)B.nchunks; c += stride) {
-    const uint4 ch = B.chunks[c];
-    const uint32_t hi = uni_m(ch.x), j0 = uni_m(ch.y), cnt = uni_m(ch.z), row0 = uni_m(ch.w);
-    const uint32_t coff = uni_m(B.lo_coff[B.half - __popc(hi)]);
-    if (lane < cnt) {
-      const uint32_t lo = t.state[coff + j0 + lane];
-      body(row0 + lane, (hi << B.nlo) | lo);
-    }
-  }
-}
 
 // ---- initialisation: z_0 = 0, z_1 = scale * (src - Ax0), q_1 = M^{-1} z_1,
 // d_{-1} = d_0 = 0, e = 0 (if given); partial sums of q_1 . z_1.
@@ -119,14 +35,16 @@ __global__ __launch_bounds__(kWG) void k_minres_init(DevBasis B, FieldArgs F, in
                                                      T* z0, T* z1, T* q1, T* d0, T* d1, T* e,
                                                      double* __restrict__ partials) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const MTables t = msetup(B, F, smem);
+  const RowTables t = setup_tables(B, F, smem);
   __syncthreads();
   double acc = 0.0;
-  mfor_rows(B, t, [&](uint32_t row, uint32_t a) {
+  for_rows(B, t, [&](uint32_t row, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t a) {
     double zi = src[row];
     if (ax0) zi -= (double)ax0[row];
     const T zt = (T)(scale * zi);
-    const T qt = (T)((double)zt / mprecond(B, F, t, kind, a));
+    int na;
+    const double dsh = row_diag<0>(B, F, t, a, na);
+    const T qt = (T)((double)zt / precond_value(kind, dsh, na));
     z0[row] = (T)0;
     z1[row] = zt;
     q1[row] = qt;
@@ -135,7 +53,7 @@ __global__ __launch_bounds__(kWG) void k_minres_init(DevBasis B, FieldArgs F, in
     if (e) e[row] = (T)0;
     acc += (double)qt * (double)zt;
   });
-  const double s = block_sum_m(acc, t.red);
+  const double s = block_sum_all(acc, t.red);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 
@@ -173,21 +91,23 @@ __global__ __launch_bounds__(kWG) void k_minres_zq(DevBasis B, FieldArgs F, int 
                                                    double* __restrict__ part2) {
   if (Sin->done) return;
   extern __shared__ __align__(16) unsigned char smem[];
-  const MTables t = msetup(B, F, smem);
+  const RowTables t = setup_tables(B, F, smem);
   const double qp = reduce_partials(part1, P1, t.red);
   const double beta = Sin->beta, beta_prev = Sin->beta_prev;
   const double alpha = qp / (beta * beta);
   const double c1 = 1.0 / beta, c2 = alpha / beta, c3 = beta / beta_prev;
   double acc = 0.0;
-  mfor_rows(B, t, [&](uint32_t row, uint32_t a) {
+  for_rows(B, t, [&](uint32_t row, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t a) {
     const double zn = c1 * (double)p[row] - c2 * (double)zk[row] - c3 * (double)zkm1[row];
     const T zt = (T)zn;
-    const T qt = (T)((double)zt / mprecond(B, F, t, kind, a));
+    int na;
+    const double dsh = row_diag<0>(B, F, t, a, na);
+    const T qt = (T)((double)zt / precond_value(kind, dsh, na));
     zkm1[row] = zt;
     qnext[row] = qt;
     acc += (double)qt * (double)zt;
   });
-  const double s = block_sum_m(acc, t.red);
+  const double s = block_sum_all(acc, t.red);
   if (threadIdx.x == 0) part2[blockIdx.x] = s;
 }
 
@@ -246,6 +166,196 @@ __global__ __launch_bounds__(kWG) void k_minres_dx(int64_t n, const MinresState*
   }
 }
 
+// ---- the whole solve in one cooperative launch ------------------------------
+// Every workgroup owns the rows of its chunks (grid-stride over chunks) for
+// every vector update, and meets the others at two grid barriers per
+// iteration:
+//   phase A: d_{k-1}, x_{k-1} update of the previous iteration on own rows;
+//            p = A q_k on own rows (gathers read all of q_k); partial q_k.p
+//   -- barrier --
+//   phase B: alpha_k from all partials; z_{k+1}, q_{k+1} on own rows; partial
+//            q_{k+1}.z_{k+1}
+//   -- barrier --
+//   phase C: beta_{k+1} and the Givens rotation from all partials (every
+//            workgroup computes the same scalars in the same order, so all
+//            leave the loop at the same k)
+// A barrier is an arrival counter; a workgroup that waits longer than about
+// one second marks the launch failed and leaves, so the launch always ends.
+template <typename T>
+struct PersistArgs {
+  T* z[2];
+  T* q[2];
+  T* d[2];
+  T* p;
+  T* x;
+  double* part1;
+  double* part2;
+  unsigned int* bar;     // arrival counter, zero at launch
+  int* fail;             // set on a barrier timeout
+  MinresState* S;        // S[0]: state after initialisation; final state written back
+  double tol;
+  int64_t kmax;
+  int kind;
+};
+
+constexpr uint64_t kBarrierTimeoutTicks = 100000000ull;   // ~1 s of the 100 MHz clock
+
+__device__ __forceinline__ bool grid_barrier(unsigned int* bar, unsigned int target, int* fail,
+                                             int* sflag) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    atomicAdd(bar, 1u);
+    const uint64_t t0 = wall_clock64();
+    int bad = 0;
+    while (__hip_atomic_load(bar, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      __builtin_amdgcn_s_sleep(2);
+      if (__hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0 ||
+          wall_clock64() - t0 > kBarrierTimeoutTicks) {
+        bad = 1;
+        atomicExch(fail, 1);
+        break;
+      }
+    }
+    __threadfence();
+    *sflag = bad;
+  }
+  __syncthreads();
+  return *sflag == 0;
+}
+
+template <typename T, int L, int NLO>
+__global__ __launch_bounds__(kWG) void k_minres_persistent(DevBasis B, FieldArgs F,
+                                                           PersistArgs<T> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int sflag;
+  const RowTables t = setup_tables<L>(B, F, smem);
+  __syncthreads();
+  MinresState st = a.S[0];
+  const int G = gridDim.x;
+  unsigned int target = 0;
+  // previous iteration's d/x update, applied at the start of the next phase A
+  bool pending = false;
+  double pv_inv_beta = 0, pv_delta = 0, pv_eps = 0, pv_inv_gamma = 0, pv_tau = 0;
+  const uint32_t wpg = kWavesPerWG;
+  const uint32_t wave = uni(threadIdx.x >> 6);
+  const uint32_t first = blockIdx.x * wpg + wave, stride = G * wpg;
+  int64_t k = st.k;
+  bool done = st.done != 0;
+  while (!done) {
+    ++k;
+    T* qk = a.q[k & 1];
+    T* qn = a.q[(k + 1) & 1];
+    T* zk = a.z[k & 1];
+    T* zkm1 = a.z[(k + 1) & 1];
+    // ---- phase A
+    {
+      T* dprev = a.d[(k - 1) & 1];        // receives d_{k-1} (holds d_{k-3})
+      const T* dpp = a.d[k & 1];          // d_{k-2}
+      const T* qprev = qn;                // q_{k-1} (overwritten only in phase B)
+      double acc = 0.0;
+      for_rows_range(B, t, first, stride,
+                     [&](uint32_t row, uint32_t hi, uint32_t lo, uint32_t j, uint32_t block0,
+                         uint32_t s_a) {
+                       if (pending) {
+                         const double dd = ((double)qprev[row] * pv_inv_beta -
+                                            pv_delta * (double)dpp[row] -
+                                            pv_eps * (double)dprev[row]) *
+                                           pv_inv_gamma;
+                         const T dt = (T)dd;
+                         dprev[row] = dt;
+                         a.x[row] = (T)((double)a.x[row] + pv_tau * (double)dt);
+                       }
+                       const double xi = (double)qk[row];
+                       const double off = RowOps<T, L, NLO>::offdiag(B, t, qk, hi, lo, j, block0);
+                       int na;
+                       const double dsh = row_diag<L>(B, F, t, s_a, na);
+                       const T pt = (T)(dsh * xi + 0.5 * off);
+                       a.p[row] = pt;
+                       acc += xi * (double)pt;
+                     });
+      const double sblk = block_sum_all(acc, t.red);
+      if (threadIdx.x == 0) a.part1[blockIdx.x] = sblk;
+    }
+    target += G;
+    if (!grid_barrier(a.bar, target, a.fail, &sflag)) return;
+    // ---- phase B
+    const double qp = reduce_partials(a.part1, G, t.red);
+    const double beta = st.beta, beta_prev = st.beta_prev;
+    const double alpha = qp / (beta * beta);
+    {
+      const double c1 = 1.0 / beta, c2 = alpha / beta, c3 = beta / beta_prev;
+      double acc = 0.0;
+      for_rows_range(B, t, first, stride,
+                     [&](uint32_t row, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t s_a) {
+                       const double zn = c1 * (double)a.p[row] - c2 * (double)zk[row] -
+                                         c3 * (double)zkm1[row];
+                       const T zt = (T)zn;
+                       int na;
+                       const double dsh = row_diag<L>(B, F, t, s_a, na);
+                       const T qt = (T)((double)zt / precond_value(a.kind, dsh, na));
+                       zkm1[row] = zt;
+                       qn[row] = qt;
+                       acc += (double)qt * (double)zt;
+                     });
+      const double sblk = block_sum_all(acc, t.red);
+      if (threadIdx.x == 0) a.part2[blockIdx.x] = sblk;
+    }
+    target += G;
+    if (!grid_barrier(a.bar, target, a.fail, &sflag)) return;
+    // ---- phase C (scalars, identical in every workgroup)
+    const double qz = reduce_partials(a.part2, G, t.red);
+    const double beta_next = sqrt(qz);
+    const double delta = st.c * st.dhat + st.s * alpha;
+    const double gamma_hat = -st.s * st.dhat + st.c * alpha;
+    const double eps_next = st.s * beta_next;
+    const double dhat_next = st.c * beta_next;
+    const double gamma = sqrt(gamma_hat * gamma_hat + beta_next * beta_next);
+    const double c = gamma_hat / gamma;
+    const double s = beta_next / gamma;
+    const double tau = c * st.phi;
+    const double phi = -s * st.phi;
+    pending = true;
+    pv_inv_beta = 1.0 / beta;
+    pv_delta = delta;
+    pv_eps = st.eps;
+    pv_inv_gamma = 1.0 / gamma;
+    pv_tau = tau;
+    st.beta_prev = beta;
+    st.beta = beta_next;
+    st.c = c;
+    st.s = s;
+    st.dhat = dhat_next;
+    st.eps = eps_next;
+    st.phi = phi;
+    st.k = k;
+    st.bad = !isfinite(phi) || !isfinite(alpha) || !isfinite(beta_next);
+    done = st.bad || !(fabs(phi) >= a.tol && k < a.kmax);
+    st.done = done;
+  }
+  // the last iteration's d/x update (q_k is still in q[k & 1])
+  if (pending) {
+    T* dk = a.d[k & 1];                  // holds d_{k-2}
+    const T* dkm1 = a.d[(k - 1) & 1];
+    const T* qk = a.q[k & 1];
+    for_rows_range(B, t, first, stride,
+                   [&](uint32_t row, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t) {
+                     const double dd = ((double)qk[row] * pv_inv_beta -
+                                        pv_delta * (double)dkm1[row] - pv_eps * (double)dk[row]) *
+                                       pv_inv_gamma;
+                     const T dt = (T)dd;
+                     dk[row] = dt;
+                     a.x[row] = (T)((double)a.x[row] + pv_tau * (double)dt);
+                   });
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) a.S[1] = st;
+}
+
+__global__ void k_zero_u32(unsigned int* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
 // x64 += scale * e
 __global__ __launch_bounds__(kWG) void k_add_scaled_f32(int64_t n, double scale,
                                                         const float* __restrict__ e,
@@ -262,8 +372,91 @@ static int flat_grid(int64_t n) {
   return (int)(g < 1 ? 1 : g);
 }
 
-static size_t mlds(const mbl_basis_s* b) {
-  return (128 + 8) * sizeof(double) + sizeof(uint16_t) * ((size_t)1 << b->nlo);
+static size_t mlds(const mbl_basis_s* b) { return row_lds_for(b->nlo); }
+
+// One cooperative launch for the whole solve. Returns MBL_ERR_HIP with
+// *refused = true when the runtime declines the cooperative launch (the
+// caller then uses the per-iteration launches).
+template <typename T>
+static mbl_status persistent_solve(mbl_basis_s* b, const FieldArgs& F, int precond,
+                                   mbl_workspace_s* ws, T* x, double tol, int64_t kmax,
+                                   hipStream_t s, MinresState* out, bool* refused) {
+  *refused = false;
+  const void* fn = nullptr;
+  switch (b->L * 64 + b->nlo) {
+#define MBL_CASE(LL, NN)                                        \
+  case LL * 64 + NN:                                           \
+    fn = (const void*)&k_minres_persistent<T, LL, NN>;         \
+    break;
+    MBL_FAST_SPLITS(MBL_CASE)
+#undef MBL_CASE
+    default:
+      fn = (const void*)&k_minres_persistent<T, 0, 0>;
+  }
+  const size_t lds = row_lds_for(b->nlo);
+  int dev = 0, ncu = 0, per_cu = 0;
+  MBL_HIP(hipGetDevice(&dev));
+  MBL_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  MBL_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kWG, lds));
+  int G = std::min(ncu * std::max(per_cu, 0), (b->nchunks + kWavesPerWG - 1) / kWavesPerWG);
+  G = std::min(G, kMaxPartials);
+  if (G < 1) {
+    *refused = true;
+    return MBL_ERR_HIP;
+  }
+  PersistArgs<T> a;
+  for (int i = 0; i < 2; ++i) {
+    a.z[i] = (T*)ws->z[i];
+    a.q[i] = (T*)ws->q[i];
+    a.d[i] = (T*)ws->d[i];
+  }
+  a.p = (T*)ws->p;
+  a.x = x;
+  a.part1 = ws->partials1;
+  a.part2 = ws->partials2;
+  a.bar = ws->sync;
+  a.fail = reinterpret_cast<int*>(ws->sync + 1);
+  a.S = ws->state;
+  a.tol = tol;
+  a.kmax = kmax;
+  a.kind = precond;
+  hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, s, ws->sync, 4);
+  MBL_HIP(hipGetLastError());
+  DevBasis B = b->dev();
+  FieldArgs Fc = F;
+  void* args[] = {&B, &Fc, &a};
+  hipError_t e = hipLaunchCooperativeKernel(fn, dim3(G), dim3(kWG), args, (unsigned)lds, s);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *refused = true;
+    return MBL_ERR_HIP;
+  }
+  MBL_HIP(hipMemcpyAsync(&ws->h_state[2], ws->state + 1, sizeof(MinresState),
+                         hipMemcpyDeviceToHost, s));
+  MBL_HIP(hipMemcpyAsync(&ws->h_state[3], ws->sync, sizeof(unsigned int) * 4,
+                         hipMemcpyDeviceToHost, s));
+  MBL_HIP(hipStreamSynchronize(s));
+  const int fail = reinterpret_cast<const int*>(&ws->h_state[3])[1];
+  if (fail) {
+    set_error("grid barrier timed out in the persistent MINRES launch");
+    return MBL_ERR_HIP;
+  }
+  *out = ws->h_state[2];
+  return MBL_OK;
+}
+
+// The single cooperative launch pays two grid barriers per iteration on one
+// arrival counter, whose atomics serialise: it wins only while the grid is
+// small (few chunks). MBL_MINRES_LAUNCH=iter|persistent forces a form.
+constexpr int kPersistentMaxGrid = 64;
+static bool use_persistent(const mbl_basis_s* b) {
+  static int forced = -2;
+  if (forced == -2) {
+    const char* e = getenv("MBL_MINRES_LAUNCH");
+    forced = !e ? -1 : (std::string(e) == "iter" ? 0 : (std::string(e) == "persistent" ? 1 : -1));
+  }
+  if (forced >= 0) return forced == 1;
+  return (b->nchunks + kWavesPerWG - 1) / kWavesPerWG <= kPersistentMaxGrid;
 }
 
 // Runs Alg. 2 on vectors of type T. src: FP64 right-hand side (scaled by
@@ -293,6 +486,23 @@ static mbl_status minres_core(mbl_basis_s* b, const FieldArgs& F, const double* 
   hipLaunchKernelGGL(k_minres_init_state, dim3(1), dim3(kWG), 0, s, ws->partials2, G, tol, kmax,
                      S);
   MBL_HIP(hipGetLastError());
+
+  if (use_persistent(b)) {
+    MinresState fin{};
+    bool refused = false;
+    mbl_status ps = persistent_solve<T>(b, F, precond, ws, x, tol, kmax, s, &fin, &refused);
+    if (ps == MBL_OK) {
+      *iters = fin.k;
+      *phi = fin.phi;
+      if (fin.bad) {
+        set_error("MINRES met a non-finite value (singular preconditioner or breakdown)");
+        return MBL_ERR_NUMERIC;
+      }
+      return (fabs(fin.phi) < tol) ? MBL_OK : MBL_WARN_NOCONV;
+    }
+    if (!refused) return ps;
+    clear_error();
+  }
 
   const int64_t kChunkIters = 64;
   int64_t issued = 0;

@@ -84,3 +84,17 @@ def test_tridiag_eig_clustered_and_split():
     T = np.diag(a) + np.diag(b, 1) + np.diag(b, -1)
     assert np.allclose(w, np.linalg.eigvalsh(T), atol=1e-12)
     assert np.allclose(T @ V, V * w[None, :], atol=1e-11)
+
+
+def test_single_hip_runtime_in_process():
+    """The binding loads torch's HIP runtime first, so libmbl.so resolves its
+    libamdhip64.so.7 dependency to it: one runtime serves torch's streams and
+    allocations and the library's launches."""
+    import subprocess
+    import sys
+    code = ("import sys; sys.path.insert(0, %r); import paper_2203_09732_amd; "
+            "m = open('/proc/self/maps').read(); "
+            "print(len(set(l.split()[-1] for l in m.splitlines() if 'amdhip64' in l)))") % ROOT
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "1"

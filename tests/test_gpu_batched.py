@@ -1,0 +1,145 @@
+"""Parity of the batched (interleaved, lockstep) HIP path against the CPU
+oracle and against the single-realization path, through the C ABI."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import lanczos, minres, model, twist
+from workloads import disorder_fields, gaussian_vector, start_vector
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+def _batch_inputs(L, R, h=3.0, seed0=0):
+    fields = [disorder_fields(L, h, seed0 + r) for r in range(R)]
+    sig = [0.1 * r - 0.3 for r in range(R)]
+    return fields, sig
+
+
+@pytest.mark.parametrize("L,R", [(12, 2), (12, 8), (14, 32), (16, 4), (16, 16)])
+def test_apply_batched_dense_parity(gpu, torch, L, R):
+    say(f"apply batched L={L} R={R}")
+    b = gpu.Basis(L)
+    bt = gpu.Batch(b, R)
+    fields, sig = _batch_inputs(L, R)
+    X = np.stack([gaussian_vector(b.n, 50 + r) for r in range(R)], axis=1)
+    Y = gpu.apply_H_batched(b, bt, fields, sig, torch.as_tensor(X, device="cuda")).cpu().numpy()
+    for r in range(R):
+        H = model.hamiltonian_csr(L, fields[r])
+        yref = H @ X[:, r] - sig[r] * X[:, r]
+        assert np.abs(Y[:, r] - yref).max() <= 1e-13 * np.abs(yref).max()
+    # the single-realization kernel sums in the same order
+    ys = gpu.apply_H(b, fields[R - 1], sig[R - 1], torch.as_tensor(np.ascontiguousarray(X[:, R - 1]), device="cuda"))
+    assert np.abs(ys.cpu().numpy() - Y[:, R - 1]).max() <= 1e-15 * np.abs(Y[:, R - 1]).max()
+
+
+def test_apply_batched_f32(gpu, torch):
+    say("apply batched f32 L=14 R=8")
+    L, R = 14, 8
+    b = gpu.Basis(L)
+    bt = gpu.Batch(b, R)
+    fields, sig = _batch_inputs(L, R)
+    X = np.stack([gaussian_vector(b.n, 70 + r) for r in range(R)], axis=1).astype(np.float32)
+    Y = gpu.apply_H_batched(b, bt, fields, sig, torch.as_tensor(X, device="cuda")).cpu().numpy()
+    for r in range(R):
+        yref = model.hamiltonian_csr(L, fields[r]) @ X[:, r].astype(np.float64) - sig[r] * X[:, r]
+        assert np.abs(Y[:, r] - yref).max() <= 2e-6 * np.abs(yref).max()
+
+
+@pytest.mark.parametrize("L,R", [(22, 32), (24, 8)])
+def test_apply_batched_sampled_rows_large(gpu, torch, L, R):
+    say(f"apply batched sampled L={L} R={R}")
+    b = gpu.Basis(L)
+    bt = gpu.Batch(b, R)
+    fields, sig = _batch_inputs(L, R, h=3.5)
+    g = torch.Generator(device="cuda").manual_seed(3)
+    X = torch.randn((b.n, R), dtype=torch.float64, device="cuda", generator=g)
+    Y = gpu.apply_H_batched(b, bt, fields, sig, X).cpu().numpy()
+    Xh = X.cpu().numpy()
+    states = model.sector_states(L)
+    rng = np.random.default_rng(L)
+    rows = np.unique(np.concatenate([rng.integers(0, b.n, 1500), [0, b.n - 1]]))
+    for r in (0, R // 2, R - 1):
+        st = states[rows]
+        yref = (model.diagonal(L, fields[r], st) - sig[r]) * Xh[rows, r]
+        for (a, c) in model.bonds(L):
+            anti = ((st >> (a - 1)) & 1) != ((st >> (c - 1)) & 1)
+            fl = st ^ ((1 << (a - 1)) | (1 << (c - 1)))
+            idx = np.clip(np.searchsorted(states, fl), 0, len(states) - 1)
+            yref = yref + np.where(anti, 0.5 * Xh[idx, r], 0.0)
+        assert np.abs(Y[rows, r] - yref).max() <= 1e-13 * np.abs(yref).max()
+
+
+def _problems(L, R, h=3.0, seed0=0):
+    fields, Hs, sig = [], [], []
+    for r in range(R):
+        f = disorder_fields(L, h, seed0 + r)
+        H = model.hamiltonian_csr(L, f)
+        w = np.linalg.eigvalsh(H.toarray())
+        fields.append(f)
+        Hs.append(H)
+        sig.append(0.5 * (w[0] + w[-1]))
+    return fields, Hs, sig
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_inner"])
+def test_minres_batched_parity(gpu, torch, precision):
+    say(f"minres batched L=12 R=4 {precision}")
+    L, R = 12, 4
+    fields, Hs, sig = _problems(L, R)
+    b = gpu.Basis(L)
+    bt = gpu.Batch(b, R)
+    B = np.stack([gaussian_vector(b.n, 90 + r) for r in range(R)], axis=1)
+    B /= np.linalg.norm(B, axis=0)
+    x, its, phi, st = gpu.minres_solve_batched(b, bt, fields, sig, torch.as_tensor(B, device="cuda"),
+                                               tol=1e-12, precision=precision)
+    assert st == 0 and np.all(phi < 1e-12)
+    X = x.cpu().numpy()
+    for r in range(R):
+        xd = minres.solve_dense(Hs[r].toarray(), sig[r], B[:, r])
+        assert np.linalg.norm(X[:, r] - xd) / np.linalg.norm(xd) <= 1e-8
+    if precision == "fp64":
+        # same iteration count as the single-realization solver (same recurrence)
+        xs, info = gpu.minres_solve(b, fields[1], sig[1], torch.as_tensor(np.ascontiguousarray(B[:, 1]), device="cuda"), tol=1e-12)
+        assert abs(info.iters - its[1]) <= 0.05 * its[1] + 5
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_inner"])
+def test_si_lanczos_batched_parity(gpu, torch, precision):
+    say(f"si_lanczos batched L=12 R=4 nev=4 {precision}")
+    L, R, nev = 12, 4, 4
+    fields, Hs, sig = _problems(L, R, seed0=10)
+    b = gpu.Basis(L)
+    bt = gpu.Batch(b, R, mmax=60, nevmax=nev)
+    V0 = np.stack([start_vector(b.n, r) for r in range(R)], axis=1)
+    res = gpu.si_lanczos_batched(b, bt, fields, sig, nev, v0=torch.as_tensor(V0, device="cuda"),
+                                 precision=precision)
+    say(f"  steps={res.steps} nconv={res.nconv} minres={res.minres_iters} t={res.seconds:.2f}s")
+    assert res.status == 0 and np.all(res.nconv == nev)
+    U = res.evecs.cpu().numpy()
+    z = gpu.twist_expect_batched(b, bt, res.evecs)
+    for r in range(R):
+        E, Vr = lanczos.eigenpairs_dense(Hs[r].toarray(), sig[r], nev)
+        assert np.all(np.abs(res.evals[r] - E) / np.maximum(np.abs(E), 1) <= 1e-10)
+        Ur = U[:, :, r].T
+        ov = np.abs(np.sum(Ur * Vr, axis=0))
+        assert np.all(1 - ov <= 1e-10)
+        dpsi = np.minimum(np.linalg.norm(Ur - Vr, axis=0), np.linalg.norm(Ur + Vr, axis=0))
+        zr = twist.twist_overlap(L, Vr)
+        assert np.all(np.abs(z[r] - zr) <= 2 * dpsi + 1e-12)
+        rr = lanczos.eigen_residuals(Hs[r], res.evals[r], Ur)
+        assert np.allclose(res.resid[r], rr, rtol=1e-6, atol=1e-14)
