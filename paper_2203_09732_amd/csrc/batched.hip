@@ -164,28 +164,46 @@ __device__ __forceinline__ void boffdiag(const DevBasis& B, const BTables& t,
   o1 = a1;
 }
 
-// Visit this wave's rows: body(row, hi, lo, j, block0, a, p) for lanes with a
-// valid row. Chunks are grid-strided over waves; a chunk is walked RPW rows
-// at a time.
+// Visit rows: body(row, hi, lo, j, block0, a, p) for lanes with a valid row.
+// The waves of a workgroup cooperate on consecutive chunks: a chunk (up to 64
+// rows) needs PR waves of RPW rows each, so one workgroup step covers
+// wpg / PR chunks. Workgroups of one XCD sweep that XCD's contiguous slice of
+// chunks side by side, so the XCD's live window is about 32 workgroups x 64
+// rows and the rows' low-bond and near high-bond neighbours stay in its L2.
 template <typename Body>
 __device__ __forceinline__ void bfor_rows(const DevBasis& B, const BTables& t, int R, Body body) {
-  const int PR = R >> 1, RPW = 64 / PR;
+  const uint32_t PR = (uint32_t)R >> 1, RPW = 64 / PR;
   const uint32_t lane = threadIdx.x & 63u;
   const int p = lane % PR;
   const uint32_t slot = lane / PR;
-  for_chunks(B.nchunks, [&](uint32_t c) {
+  const uint32_t wpg = blockDim.x >> 6;
+  const uint32_t wave = uni(threadIdx.x >> 6);
+  const uint32_t cps = max(1u, wpg / PR);           // chunks per workgroup step
+  const uint32_t my_chunk = wave / PR;              // this wave's chunk in the step
+  const uint32_t my_row0 = (wave % PR) * RPW;       // this wave's first row in the chunk
+  const bool wave_on = my_chunk < cps;
+  const uint32_t G = gridDim.x, nch = (uint32_t)B.nchunks;
+  uint32_t c_lo = 0, c_hi = nch, k = blockIdx.x, per = G;
+  if (G % kXcds == 0) {
+    const uint32_t span = (nch + kXcds - 1) / kXcds;
+    c_lo = min(nch, (blockIdx.x % kXcds) * span);
+    c_hi = min(nch, c_lo + span);
+    k = blockIdx.x / kXcds;
+    per = G / kXcds;
+  }
+  for (uint32_t base = c_lo + k * cps; base < c_hi; base += per * cps) {
+    const uint32_t c = base + my_chunk;
+    if (!wave_on || c >= c_hi) continue;
     const uint4 ch = B.chunks[c];
     const uint32_t hi = uni(ch.x), j0 = uni(ch.y), cnt = uni(ch.z), row0 = uni(ch.w);
     const uint32_t coff = uni(B.lo_coff[B.half - __popc(hi)]);
-    for (uint32_t s0 = 0; s0 < cnt; s0 += RPW) {
-      const uint32_t rl = s0 + slot;
-      if (rl < cnt) {
-        const uint32_t j = j0 + rl;
-        const uint32_t lo = t.state[coff + j];
-        body(row0 + rl, hi, lo, j, row0 - j0, (hi << B.nlo) | lo, p);
-      }
+    const uint32_t rl = my_row0 + slot;
+    if (rl < cnt) {
+      const uint32_t j = j0 + rl;
+      const uint32_t lo = t.state[coff + j];
+      body(row0 + rl, hi, lo, j, row0 - j0, (hi << B.nlo) | lo, p);
     }
-  });
+  }
 }
 
 // Per-realization block reduction of (acc0, acc1) for pair p; thread r < R of
