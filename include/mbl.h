@@ -183,6 +183,23 @@ mbl_status mbl_eig_residual(mbl_basis b, const double* h_host, const double* E_h
 mbl_status mbl_sigma_midpoint(mbl_basis b, const double* h_host, double rel_tol, int mmax,
                               double* emin, double* emax, double* sigma, void* stream);
 
+/* ---- eigenpair derivatives with respect to the fields h_j -------------------
+ * For an eigenpair (E, psi) of Eq. (1) (psi_dev: n doubles, any norm; the
+ * formulas use psi / ||psi||):
+ *  dE_dh_host[j]  = dE/dh_{j+1} = -<S^z_{j+1}> (Hellmann-Feynman, exact);
+ *  dz2_dh_host[j] = d|z|^2/dh_{j+1}, z = <psi|U_twist|psi> (Sec. III), by the
+ *    adjoint solve (H - E) lambda = P g with g_a = 4 c_a Re(conj(z) u_a),
+ *    P = I - psi psi^T, lambda re-projected orthogonal to psi, then
+ *    d|z|^2/dh_j = sum_a lambda_a c_a s_j(a). The solve is preconditioned
+ *    MINRES (Alg. 2) with sigma = E, tolerance tol and kmax iterations; it
+ *    needs a workspace with MINRES vectors (any mmax).
+ * z_host[2] (Re, Im of z) and info may be NULL. MBL_WARN_NOCONV if the solve
+ * missed tol. Synchronizes stream. */
+mbl_status mbl_eig_grad(mbl_basis b, const double* h_host, double E, const double* psi_dev,
+                        double tol, int64_t kmax, int precond, mbl_workspace ws,
+                        double* dE_dh_host, double* dz2_dh_host, double* z_host,
+                        mbl_minres_info* info, void* stream);
+
 /* ---- batched form: R realizations of one L in lockstep ---------------------
  * R disorder realizations of the basis's chain length, each with its own
  * fields h_r (h_host: R x L doubles, row r = realization r) and shift

@@ -5,7 +5,7 @@ This module only marshals arguments: device buffers are torch tensors on the
 current HIP device (``tensor.data_ptr()``), streams are
 ``torch.cuda.current_stream().cuda_stream``, and every step of the method
 runs in the library's kernels. Importing fails if libmbl.so has not been
-built (``python -m paper_2203_09732_amd.build``).
+built (``python paper_2203_09732_amd/build.py``).
 """
 from __future__ import annotations
 
@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libmbl.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
-        f"{LIB_PATH} is missing: build it with `python -m paper_2203_09732_amd.build` "
+        f"{LIB_PATH} is missing: build it with `python paper_2203_09732_amd/build.py` "
         "(hipcc, gfx950). There is no fallback implementation.")
 
 # One HIP runtime per process: torch ships its own libamdhip64 (same SONAME,
@@ -490,3 +490,77 @@ def twist_expect_batched(basis: Basis, batch: Batch, U, stream=None) -> np.ndarr
            "mbl_twist_expect_batched")
     z = z.reshape(batch.R, nvec, 2)
     return z[..., 0] + 1j * z[..., 1]
+
+
+# ---------------------------------------------------------------- derivatives
+_sig("mbl_eig_grad", _i32, [_vp, _dp, _d, _vp, _d, _i64, C.c_int, _vp, _dp, _dp, _dp,
+                            C.POINTER(MinresInfo), _vp])
+
+
+def eig_grad(basis: Basis, h, E: float, psi, tol: float = 1e-10, kmax: int = 10_000_000,
+             precond: str = "row", ws: Workspace | None = None, stream=None):
+    """(dE/dh, d|z|^2/dh, z, info) for the eigenpair (E, psi), psi an (n,) FP64 tensor."""
+    import torch
+    _need_cuda(psi, torch.float64, basis.n, "psi")
+    ws = ws or Workspace(basis, 0)
+    L = basis.L
+    dE = np.zeros(L)
+    dz2 = np.zeros(L)
+    z = np.zeros(2)
+    info = MinresInfo()
+    ha, hp = _f64(h)
+    st = lib.mbl_eig_grad(basis.handle, hp, float(E), _ptr(psi), float(tol), int(kmax),
+                          PRECOND[precond], ws.handle, dE.ctypes.data_as(_dp),
+                          dz2.ctypes.data_as(_dp), z.ctypes.data_as(_dp), C.byref(info),
+                          _stream(stream))
+    _check(st, "mbl_eig_grad")
+    return dE, dz2, complex(z[0], z[1]), SolveInfo(st, info.iters, info.restarts, info.phi,
+                                                   info.true_res)
+
+
+class EigPair:
+    """Differentiable map h -> (E, |z|^2) of one eigenpair near sigma.
+
+    ``EigPair(basis, sigma, nev, which)(h)`` runs shift-invert Lanczos for the
+    nev pairs nearest sigma and returns the eigenvalue and |z|^2 of pair
+    ``which`` (ascending order) as torch scalars; backward() obtains dE/dh
+    (Hellmann-Feynman) and d|z|^2/dh (one adjoint MINRES solve) from the
+    library. ``h`` is a float64 CPU or GPU tensor of length L."""
+
+    def __init__(self, basis: Basis, sigma: float, nev: int = 1, which: int = 0,
+                 grad_tol: float = 1e-10, **si_kw):
+        self.basis, self.sigma, self.nev, self.which = basis, sigma, nev, which
+        self.grad_tol, self.si_kw = grad_tol, si_kw
+
+    def __call__(self, h):
+        return _EigPairFn.apply(h, self)
+
+
+def _make_fn():
+    import torch
+
+    class _Fn(torch.autograd.Function):
+        @staticmethod
+        def forward(ctx, h, spec):
+            hh = h.detach().cpu().numpy().astype(np.float64)
+            res = si_lanczos(spec.basis, hh, spec.sigma, spec.nev, **spec.si_kw)
+            psi = res.evecs[:, spec.which].contiguous()
+            E = float(res.evals[spec.which])
+            z = twist_expect(spec.basis, psi)[0]
+            ctx.spec, ctx.E, ctx.hh = spec, E, hh
+            ctx.psi = psi
+            ctx.h_device = h.device
+            return (torch.tensor(E, dtype=torch.float64, device=h.device),
+                    torch.tensor(abs(z) ** 2, dtype=torch.float64, device=h.device))
+
+        @staticmethod
+        def backward(ctx, gE, gz2):
+            dE, dz2, _, _ = eig_grad(ctx.spec.basis, ctx.hh, ctx.E, ctx.psi, tol=ctx.spec.grad_tol)
+            gh = (gE.detach().cpu().double() * torch.from_numpy(dE)
+                  + gz2.detach().cpu().double() * torch.from_numpy(dz2))
+            return gh.to(ctx.h_device), None
+
+    return _Fn
+
+
+_EigPairFn = _make_fn()

@@ -1,6 +1,6 @@
 """Builds libmbl.so for gfx950 with hipcc, in-tree.
 
-    python -m paper_2203_09732_amd.build        (or build() from Python)
+    python paper_2203_09732_amd/build.py        (or build() from Python)
 
 Each .hip translation unit under csrc/ is compiled in parallel and linked
 into paper_2203_09732_amd/libmbl.so. It always recompiles.
@@ -26,7 +26,7 @@ COMMON = [
     "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas",
 ]
 
-SOURCES = ["kernels.hip", "minres.hip", "lanczos.hip", "batched.hip", "api.hip"]
+SOURCES = ["kernels.hip", "minres.hip", "lanczos.hip", "batched.hip", "adjoint.hip", "api.hip"]
 
 
 def _compile(src: str) -> str:

@@ -122,6 +122,7 @@ static void free_ws(mbl_workspace_s* w) {
   hipFree(w->ycoef);
   hipFree(w->partials1);
   hipFree(w->partials2);
+  hipFree(w->partials3);
   hipFree(w->red_out);
   hipFree(w->state);
   hipFree(w->sync);
@@ -168,6 +169,7 @@ static mbl_status create_ws(mbl_basis_s* b, int mmax, int precision, bool minres
   A(&w->ycoef, std::max<size_t>(64, (size_t)(mmax + 1) * (size_t)(mmax + 1)));
   A(&w->partials1, (size_t)kMaxPartials * 64);
   A(&w->partials2, std::max<size_t>((size_t)kMaxPartials * 64, (size_t)512 * (mmax + 1)));
+  A(&w->partials3, (size_t)kMaxPartials);
   A(&w->red_out, 256);
   A(&w->state, 2);
   A(&w->sync, 4);

@@ -30,11 +30,14 @@ namespace mbl {
 template <typename T, int MODE, bool GUARD, int L, int NLO>
 __global__ __launch_bounds__(kWG) void k_apply(DevBasis B, FieldArgs F, const MinresState* S,
                                                const T* __restrict__ x, T* __restrict__ y,
-                                               double* __restrict__ partials) {
+                                               double* __restrict__ partials, Defl D) {
   if (GUARD && S->done) return;
   extern __shared__ __align__(16) unsigned char smem[];
   const RowTables t = setup_tables<L>(B, F, smem);
   __syncthreads();
+  // rank-one term theta v (v . x) of a deflated MINRES operator
+  double dcoef = 0.0;
+  if (GUARD && D.v) dcoef = D.theta * reduce_partials(D.c_part, D.P, t.red);
   double acc = 0.0;
   for_rows(B, t, [&](uint32_t row, uint32_t hi, uint32_t lo, uint32_t j, uint32_t block0,
                      uint32_t a) {
@@ -42,7 +45,9 @@ __global__ __launch_bounds__(kWG) void k_apply(DevBasis B, FieldArgs F, const Mi
     const double off = RowOps<T, L, NLO>::offdiag(B, t, x, hi, lo, j, block0);
     int na;
     const double dsh = row_diag<L>(B, F, t, a, na);
-    const T yt = (T)(dsh * xi + 0.5 * off);
+    double yv = dsh * xi + 0.5 * off;
+    if (GUARD && D.v) yv += dcoef * D.v[row];
+    const T yt = (T)yv;
     y[row] = yt;
     if (MODE == 1) acc += xi * (double)yt;
     if (MODE == 2) acc += (double)yt * (double)yt;
@@ -240,7 +245,8 @@ static int dense_grid(int64_t n) {
 // launch the (L, NLO) instance matching the basis, else the runtime form
 template <typename T, int MODE, bool GUARD>
 static hipError_t apply_dispatch(const mbl_basis_s* b, const FieldArgs& F, const MinresState* S,
-                                 const T* x, T* y, double* partials, hipStream_t s) {
+                                 const T* x, T* y, double* partials, hipStream_t s,
+                                 const Defl& D = Defl{}) {
   const dim3 g(row_grid(b)), blk(kWG);
   const size_t lds = row_lds_bytes(b);
   const DevBasis B = b->dev();
@@ -248,13 +254,13 @@ static hipError_t apply_dispatch(const mbl_basis_s* b, const FieldArgs& F, const
 #define MBL_CASE(LL, NN)                                                                     \
   case LL * 64 + NN:                                                                        \
     hipLaunchKernelGGL((k_apply<T, MODE, GUARD, LL, NN>), g, blk, lds, s, B, F, S, x, y,  \
-                       partials);                                                           \
+                       partials, D);                                                        \
     return hipGetLastError();
     MBL_FAST_SPLITS(MBL_CASE)
 #undef MBL_CASE
     default:
       hipLaunchKernelGGL((k_apply<T, MODE, GUARD, 0, 0>), g, blk, lds, s, B, F, S, x, y,
-                         partials);
+                         partials, D);
       return hipGetLastError();
   }
 }
@@ -274,15 +280,15 @@ template hipError_t launch_apply<float>(const mbl_basis_s*, const FieldArgs&, co
 
 template <typename T>
 hipError_t launch_minres_apply(const mbl_basis_s* b, const FieldArgs& F, const MinresState* S,
-                               const T* q, T* p, double* partials, hipStream_t s) {
-  return apply_dispatch<T, 1, true>(b, F, S, q, p, partials, s);
+                               const T* q, T* p, double* partials, const Defl& D, hipStream_t s) {
+  return apply_dispatch<T, 1, true>(b, F, S, q, p, partials, s, D);
 }
 template hipError_t launch_minres_apply<double>(const mbl_basis_s*, const FieldArgs&,
                                                 const MinresState*, const double*, double*,
-                                                double*, hipStream_t);
+                                                double*, const Defl&, hipStream_t);
 template hipError_t launch_minres_apply<float>(const mbl_basis_s*, const FieldArgs&,
                                                const MinresState*, const float*, float*, double*,
-                                               hipStream_t);
+                                               const Defl&, hipStream_t);
 
 hipError_t launch_precond(const mbl_basis_s* b, const FieldArgs& F, int kind, const double* z,
                           double* q, hipStream_t s) {

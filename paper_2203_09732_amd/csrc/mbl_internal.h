@@ -73,6 +73,16 @@ struct FieldArgs {
   double sigma;
 };
 
+// Rank-one term theta * v v^T added to the operator of a MINRES solve
+// (deflation of a known near-null vector v). c_part holds per-workgroup
+// partial sums of v . q for the current q.
+struct Defl {
+  const double* v = nullptr;
+  double theta = 0.0;
+  const double* c_part = nullptr;
+  int P = 0;
+};
+
 // MINRES scalar state after iteration k (two slots, k & 1).
 struct MinresState {
   double beta_prev, beta, c, s, dhat, eps, phi;
@@ -122,6 +132,7 @@ struct mbl_workspace_s {
   // reductions and MINRES state
   double* partials1 = nullptr;   // kMaxPartials * 64
   double* partials2 = nullptr;   // kMaxPartials * 64
+  double* partials3 = nullptr;   // kMaxPartials
   double* red_out = nullptr;     // 256 doubles
   mbl::MinresState* state = nullptr;  // 2 slots
   unsigned int* sync = nullptr;       // grid barrier counter + failure flag
@@ -146,7 +157,7 @@ hipError_t launch_apply(const mbl_basis_s* b, const FieldArgs& F, const T* x, T*
                         double* partials, int* nparts, hipStream_t s);
 template <typename T>
 hipError_t launch_minres_apply(const mbl_basis_s* b, const FieldArgs& F, const MinresState* S,
-                               const T* q, T* p, double* partials, hipStream_t s);
+                               const T* q, T* p, double* partials, const Defl& D, hipStream_t s);
 hipError_t launch_precond(const mbl_basis_s* b, const FieldArgs& F, int kind, const double* z,
                           double* q, hipStream_t s);
 hipError_t launch_states(const mbl_basis_s* b, uint32_t* states, hipStream_t s);
@@ -179,7 +190,8 @@ mbl_status reduce_to_host(mbl_workspace_s* ws, const double* partials, int npart
 // MINRES driver (minres.hip)
 mbl_status minres_run(mbl_basis_s* b, const double* h_host, double sigma, const double* rhs,
                       double* x, double tol, int64_t kmax, int precision, int precond,
-                      bool x0_zero, mbl_workspace_s* ws, mbl_minres_info* info, hipStream_t s);
+                      bool x0_zero, mbl_workspace_s* ws, mbl_minres_info* info, hipStream_t s,
+                      const double* defl = nullptr, double theta = 0.0);
 
 // host symmetric tridiagonal eigensolver (implicit QL with shifts)
 int tridiag_eig(int k, const double* alpha, const double* beta, double* evals, double* evecs);

@@ -33,11 +33,13 @@ __global__ __launch_bounds__(kWG) void k_minres_init(DevBasis B, FieldArgs F, in
                                                      const double* __restrict__ src,
                                                      const T* __restrict__ ax0, double scale,
                                                      T* z0, T* z1, T* q1, T* d0, T* d1, T* e,
-                                                     double* __restrict__ partials) {
+                                                     double* __restrict__ partials,
+                                                     const double* __restrict__ dv,
+                                                     double* __restrict__ part3) {
   extern __shared__ __align__(16) unsigned char smem[];
   const RowTables t = setup_tables(B, F, smem);
   __syncthreads();
-  double acc = 0.0;
+  double acc = 0.0, acc3 = 0.0;
   for_rows(B, t, [&](uint32_t row, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t a) {
     double zi = src[row];
     if (ax0) zi -= (double)ax0[row];
@@ -52,9 +54,14 @@ __global__ __launch_bounds__(kWG) void k_minres_init(DevBasis B, FieldArgs F, in
     d1[row] = (T)0;
     if (e) e[row] = (T)0;
     acc += (double)qt * (double)zt;
+    if (dv) acc3 += dv[row] * (double)qt;
   });
   const double s = block_sum_all(acc, t.red);
   if (threadIdx.x == 0) partials[blockIdx.x] = s;
+  if (dv) {
+    const double s3 = block_sum_all(acc3, t.red);
+    if (threadIdx.x == 0) part3[blockIdx.x] = s3;
+  }
 }
 
 __global__ void k_minres_init_state(const double* __restrict__ partials, int P, double tol,
@@ -88,7 +95,9 @@ __global__ __launch_bounds__(kWG) void k_minres_zq(DevBasis B, FieldArgs F, int 
                                                    const double* __restrict__ part1, int P1,
                                                    const T* __restrict__ p, const T* __restrict__ zk,
                                                    T* __restrict__ zkm1, T* __restrict__ qnext,
-                                                   double* __restrict__ part2) {
+                                                   double* __restrict__ part2,
+                                                   const double* __restrict__ dv,
+                                                   double* __restrict__ part3) {
   if (Sin->done) return;
   extern __shared__ __align__(16) unsigned char smem[];
   const RowTables t = setup_tables(B, F, smem);
@@ -96,7 +105,7 @@ __global__ __launch_bounds__(kWG) void k_minres_zq(DevBasis B, FieldArgs F, int 
   const double beta = Sin->beta, beta_prev = Sin->beta_prev;
   const double alpha = qp / (beta * beta);
   const double c1 = 1.0 / beta, c2 = alpha / beta, c3 = beta / beta_prev;
-  double acc = 0.0;
+  double acc = 0.0, acc3 = 0.0;
   for_rows(B, t, [&](uint32_t row, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t a) {
     const double zn = c1 * (double)p[row] - c2 * (double)zk[row] - c3 * (double)zkm1[row];
     const T zt = (T)zn;
@@ -106,9 +115,14 @@ __global__ __launch_bounds__(kWG) void k_minres_zq(DevBasis B, FieldArgs F, int 
     zkm1[row] = zt;
     qnext[row] = qt;
     acc += (double)qt * (double)zt;
+    if (dv) acc3 += dv[row] * (double)qt;
   });
   const double s = block_sum_all(acc, t.red);
   if (threadIdx.x == 0) part2[blockIdx.x] = s;
+  if (dv) {
+    const double s3 = block_sum_all(acc3, t.red);
+    if (threadIdx.x == 0) part3[blockIdx.x] = s3;
+  }
 }
 
 // ---- step 3: Givens rotation, d_k, x_k (flat kernel) -----------------------
@@ -465,7 +479,7 @@ template <typename T>
 static mbl_status minres_core(mbl_basis_s* b, const FieldArgs& F, const double* src,
                               double scale, T* x, bool x0_zero, double tol, int64_t kmax,
                               int precond, mbl_workspace_s* ws, int64_t* iters, double* phi,
-                              hipStream_t s) {
+                              hipStream_t s, const double* defl = nullptr, double theta = 0.0) {
   const int64_t n = b->n;
   T* Z[2] = {(T*)ws->z[0], (T*)ws->z[1]};
   T* Q[2] = {(T*)ws->q[0], (T*)ws->q[1]};
@@ -476,18 +490,25 @@ static mbl_status minres_core(mbl_basis_s* b, const FieldArgs& F, const double* 
   const DevBasis B = b->dev();
   MinresState* S = ws->state;
 
-  // p = A x0 (skipped when x0 = 0)
+  // p = A x0 (skipped when x0 = 0; a deflated solve starts from x0 = 0)
   if (!x0_zero) MBL_HIP(launch_apply<T>(b, F, x, P, 0, nullptr, nullptr, s));
+  Defl dfl;
+  if (defl) {
+    dfl.v = defl;
+    dfl.theta = theta;
+    dfl.c_part = ws->partials3;
+    dfl.P = G;
+  }
   // z_0 = 0 in Z[0], z_1 in Z[1], q_1 in Q[1], d_{-1} in D[1], d_0 in D[0]
   hipLaunchKernelGGL((k_minres_init<T>), dim3(G), dim3(kWG), lds, s, B, F, precond, src,
                      x0_zero ? (const T*)nullptr : (const T*)P, scale, Z[0], Z[1], Q[1], D[0],
-                     D[1], x0_zero ? x : (T*)nullptr, ws->partials2);
+                     D[1], x0_zero ? x : (T*)nullptr, ws->partials2, defl, ws->partials3);
   MBL_HIP(hipGetLastError());
   hipLaunchKernelGGL(k_minres_init_state, dim3(1), dim3(kWG), 0, s, ws->partials2, G, tol, kmax,
                      S);
   MBL_HIP(hipGetLastError());
 
-  if (use_persistent(b)) {
+  if (use_persistent(b) && !defl) {
     MinresState fin{};
     bool refused = false;
     mbl_status ps = persistent_solve<T>(b, F, precond, ws, x, tol, kmax, s, &fin, &refused);
@@ -529,9 +550,9 @@ static mbl_status minres_core(mbl_basis_s* b, const FieldArgs& F, const double* 
       T* zkm1 = Z[(k + 1) & 1];
       T* dkm1 = D[(k - 1) & 1];
       T* dkm2 = D[k & 1];
-      MBL_HIP(launch_minres_apply<T>(b, F, Sin, qk, P, ws->partials1, s));
+      MBL_HIP(launch_minres_apply<T>(b, F, Sin, qk, P, ws->partials1, dfl, s));
       hipLaunchKernelGGL((k_minres_zq<T>), dim3(G), dim3(kWG), lds, s, B, F, precond, Sin,
-                         ws->partials1, G, P, zk, zkm1, qn, ws->partials2);
+                         ws->partials1, G, P, zk, zkm1, qn, ws->partials2, defl, ws->partials3);
       hipLaunchKernelGGL((k_minres_dx<T>), dim3(FG), dim3(kWG), 0, s, n, Sin, Sout,
                          ws->partials1, G, ws->partials2, G, tol, kmax, qk, dkm1, dkm2, x);
     }
@@ -566,7 +587,8 @@ static mbl_status minres_core(mbl_basis_s* b, const FieldArgs& F, const double* 
 
 mbl_status minres_run(mbl_basis_s* b, const double* h_host, double sigma, const double* rhs,
                       double* x, double tol, int64_t kmax, int precision, int precond,
-                      bool x0_zero, mbl_workspace_s* ws, mbl_minres_info* info, hipStream_t s) {
+                      bool x0_zero, mbl_workspace_s* ws, mbl_minres_info* info, hipStream_t s,
+                      const double* defl, double theta) {
   const FieldArgs F = make_fields(b, h_host, sigma);
   const int64_t n = b->n;
   mbl_minres_info inf{};
@@ -574,7 +596,8 @@ mbl_status minres_run(mbl_basis_s* b, const double* h_host, double sigma, const 
   if (precision == MBL_FP64) {
     int64_t it = 0;
     double phi = 0;
-    st = minres_core<double>(b, F, rhs, 1.0, x, x0_zero, tol, kmax, precond, ws, &it, &phi, s);
+    st = minres_core<double>(b, F, rhs, 1.0, x, x0_zero, tol, kmax, precond, ws, &it, &phi, s,
+                             defl, theta);
     if (st < 0) return st;
     inf.iters = it;
     inf.phi = phi;
