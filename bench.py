@@ -34,6 +34,38 @@ import numpy as np  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 WORKLOAD = "mixed_L22"
+COUNTERS = os.path.join(ROOT, "profiles", "bapply_L22_R32_counters.md")
+
+
+def kernel_source_hash() -> str:
+    """sha256 over the kernel sources (file name, then content, sorted)."""
+    import glob
+    import hashlib
+    files = sorted(glob.glob(os.path.join(ROOT, "paper_2203_09732_amd", "csrc", "*.hip")) +
+                   glob.glob(os.path.join(ROOT, "paper_2203_09732_amd", "csrc", "*.h")) +
+                   [os.path.join(ROOT, "include", "mbl.h")])
+    h = hashlib.sha256()
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from the committed counter summary, or None when
+    the kernel sources or the kernel instance differ from the ones counted."""
+    try:
+        fields = dict(line.split(": ", 1) for line in open(COUNTERS).read().splitlines()
+                      if ": " in line and line.split(": ", 1)[0] in
+                      ("source_sha256", "kernel", "traffic_bytes_per_launch"))
+    except OSError:
+        return None
+    if fields.get("source_sha256", "").strip() != kernel_source_hash():
+        return None
+    if fields.get("kernel", "").strip() != kernel:
+        return None
+    return int(fields["traffic_bytes_per_launch"])
 
 
 def parse():
@@ -42,8 +74,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--realizations", type=int, default=32)
-    ap.add_argument("--eig", action="store_true", help="also time an L=22 eigensolve")
-    ap.add_argument("--eig-nev", type=int, default=2)
+    ap.add_argument("--eig-L", type=int, default=16, help="chain length of the eigenpair leg")
+    ap.add_argument("--eig-nev", type=int, default=6)
+    ap.add_argument("--eig-R", type=int, default=16, help="realizations of the batched eigen leg")
+    ap.add_argument("--no-eig", action="store_true", help="skip the eigenpair leg")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--minres-iters", type=int, default=1000)
     ap.add_argument("--profile-run", action="store_true",
@@ -73,6 +107,79 @@ def cpu_baseline(fields, sigmas, L, budget_s=15.0):
         "sample": f"{done} products (H - sigma) x of realization 0 at L={L} with the oracle's "
                   f"scipy CSR matrix (build {t_build:.1f} s excluded), {dt:.1f} s",
     }
+
+
+def progress(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def eig_leg(mbl, torch, L, nev, R):
+    """Seconds per converged eigenpair (explicit FP64 residual <= 1e-10 escale)
+    of the whole path (sigma, SI-Lanczos with MINRES, Ritz vectors, residual
+    checks, twist) on L, one realization per launch and R in lockstep, FP64 and
+    FP32-inner MINRES."""
+    from workloads import disorder_fields
+    from paper_2203_09732_amd import tune
+    h = 3.0
+    fields = [disorder_fields(L, h, 5000 + r) for r in range(R)]
+    out = {"L": L, "nev": nev, "h": h, "eig_tol": 1e-10, "minres_tol": 1e-12}
+    for prec in ("fp64", "fp32_inner"):
+        b = mbl.Basis(L)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        lo, hi, sg = mbl.sigma_midpoint(b, fields[0], 1e-12)
+        res = mbl.si_lanczos(b, fields[0], sg, nev, escale=max(abs(lo), abs(hi)), seed=7,
+                             precision=prec)
+        mbl.twist_expect(b, res.evecs)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        progress(f"eig leg L={L} single {prec}: {dt:.1f} s, {res.nconv} pairs")
+        out["single_" + prec] = {"value": round(dt / max(res.nconv, 1), 4), "nconv": int(res.nconv),
+                                 "realizations": 1, "seconds": round(dt, 3), "steps": int(res.steps),
+                                 "minres_iters": int(res.minres_iters)}
+        bb = mbl.Basis(L, tune.best_lo_bits(L, R, "fp64" if prec == "fp64" else "fp32"))
+        mmax = min(bb.n, 3 * nev + 40)
+        bt = mbl.Batch(bb, R, mmax=mmax, nevmax=nev)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        sig, esc = [], []
+        for f in fields:
+            lo, hi, sg = mbl.sigma_midpoint(bb, f, 1e-12)
+            sig.append(sg)
+            esc.append(max(abs(lo), abs(hi)))
+        resb = mbl.si_lanczos_batched(bb, bt, fields, sig, nev, mmax=mmax, escale=esc, seed=7,
+                                      precision=prec)
+        mbl.twist_expect_batched(bb, bt, resb.evecs)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        nconv = int(resb.nconv.sum())
+        progress(f"eig leg L={L} batched R={R} {prec}: {dt:.1f} s, {nconv} pairs")
+        out["batched_" + prec] = {"value": round(dt / max(nconv, 1), 4), "nconv": nconv,
+                                  "realizations": R, "seconds": round(dt, 3),
+                                  "steps_max": int(resb.steps.max()),
+                                  "minres_iters": int(resb.minres_iters)}
+    out["unit"] = "s per converged eigenpair"
+    return out
+
+
+# MINRES iterations of one tol-1e-12 solve at L=22, h=3.5, sigma at the
+# midpoint (realization 0), measured on MI355X with minres_solve.
+L22_ITERS = {"fp64": 946392, "fp32_inner": 3429022}
+# shift-invert Lanczos steps for 20 pairs at eig_tol 1e-10 with exact solves
+# (oracle calibration at L=16); the count is nearly independent of L.
+L22_STEPS_20 = 47
+
+
+def l22_projection(minres):
+    """Seconds per eigenpair at L=22 (20 pairs) projected from the per-iteration
+    times measured in this run and the measured L=22 iteration counts."""
+    out = {"kind": "projection: live us/iteration x measured iterations per solve x steps / pairs",
+           "steps": L22_STEPS_20, "pairs": 20, "iters_per_solve": L22_ITERS}
+    for form, key in (("single_fp64", "fp64"), ("single_fp32_inner", "fp32_inner"),
+                      ("batched_fp64", "fp64"), ("batched_fp32_inner", "fp32_inner")):
+        us = minres[form]["us_per_realization_iter"]
+        out[form] = round(us * 1e-6 * L22_ITERS[key] * L22_STEPS_20 / 20, 1)
+    return out
 
 
 def main():
@@ -124,6 +231,7 @@ def main():
                           "bytes_per_copy": 16 * n * R}))
         return
 
+    progress(f"setup done: L={L} n={n} R={R} lo_bits={basis.lo_bits}")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -143,6 +251,7 @@ def main():
     achieved = bytes_per_launch / avg_launch / 1e9
     value = achieved
 
+    progress(f"batched apply: {achieved:.1f} GB/s ({avg_launch * 1e6:.1f} us per launch)")
     # the same products one realization per launch (single-realization kernel)
     xs = [X[:, r].contiguous() for r in range(R)]
     ys = [torch.empty_like(xs[0]) for _ in range(R)]
@@ -171,6 +280,7 @@ def main():
                                    kmax=args.minres_iters, precision=prec, ws=ws)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
+        progress(f"minres single {prec}: {dt / max(info.iters, 1) * 1e6:.1f} us/iter")
         minres["single_" + prec] = {"iters": int(info.iters),
                                     "us_per_iter": round(dt / max(info.iters, 1) * 1e6, 2),
                                     "us_per_realization_iter": round(dt / max(info.iters, 1) * 1e6, 2)}
@@ -183,6 +293,7 @@ def main():
         torch.cuda.synchronize()
         dt = time.perf_counter() - t
         it = int(its.max())
+        progress(f"minres batched {prec}: {dt / max(it, 1) * 1e6:.1f} us/iter")
         minres["batched_" + prec] = {"iters": it, "realizations": R,
                                      "us_per_iter": round(dt / max(it, 1) * 1e6, 2),
                                      "us_per_realization_iter": round(dt / max(it, 1) / R * 1e6, 2)}
@@ -205,7 +316,8 @@ def main():
                    "sigma": "spectral midpoint per realization",
                    "step": "one batched apply_H over all realizations (interleaved n x R)"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(f"k_bapply<double,0,false,{L},{basis.lo_bits}>"),
                      "kernel": f"k_bapply<double,0,false,{L},{basis.lo_bits}>",
                      "bytes_per_launch": bytes_per_launch, "avg_launch_us": round(avg_launch * 1e6, 3)},
         "apply_single_realization": {"GBps": round(16.0 * n / single_s / 1e9, 1),
@@ -213,16 +325,11 @@ def main():
         "minres_L22": minres,
         "wall_s": round(wall, 3),
     }
-    if args.eig:
-        from workloads import start_vector
-        v0 = torch.as_tensor(start_vector(n, 0), device=dev)
-        t = time.perf_counter()
-        res = mbl.si_lanczos(basis, fields[0], sigmas[0], args.eig_nev, v0=v0)
-        dt = time.perf_counter() - t
-        out["sec_per_eigenpair_L22_fp64"] = {"value": round(dt / max(res.nconv, 1), 2), "nev": args.eig_nev,
-                                             "nconv": res.nconv, "steps": res.steps,
-                                             "minres_iters": res.minres_iters}
+    if not args.no_eig:
+        out["sec_per_eigenpair"] = eig_leg(mbl, torch, args.eig_L, args.eig_nev, args.eig_R)
+        out["sec_per_eigenpair_L22_projection"] = l22_projection(minres)
     if not args.no_cpu:
+        progress("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(fields, sigmas, L)
     print(json.dumps(out))
 

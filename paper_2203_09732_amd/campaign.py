@@ -1,0 +1,111 @@
+"""Disorder campaigns: many realizations of uneven chain length.
+
+Realizations are grouped by L; each group is solved in batches of R
+realizations (a power of two, as large as the kernels' LDS budget allows for
+that L) by the lockstep shift-invert Lanczos of the library, after
+sigma = (E_min + E_max)/2 has been found for each realization (Sec. IV A).
+A batch that is not full is padded with copies of its last realization,
+whose results are dropped. One JSON line per realization is appended to an
+optional results file; realizations already present there are skipped, so an
+interrupted campaign resumes where it stopped.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import Basis, Batch, si_lanczos_batched, sigma_midpoint, twist_expect_batched
+from . import tune
+
+MAX_R = 32
+
+
+@dataclass
+class Task:
+    index: int
+    L: int
+    h: float
+    fields: np.ndarray
+
+
+def widest_batch(L: int, want: int) -> int:
+    """Largest power of two <= min(want, 32) whose field tables fit the LDS budget."""
+    R = 2
+    while R * 2 <= min(max(want, 2), MAX_R) and (R * 2) * 16 * ((L + 3) // 4) * 8 <= 30 * 1024:
+        R *= 2
+    return R
+
+
+def _done_indices(path):
+    if not path or not os.path.exists(path):
+        return set()
+    out = set()
+    with open(path) as fh:
+        for line in fh:
+            try:
+                out.add(int(json.loads(line)["index"]))
+            except Exception:
+                continue
+    return out
+
+
+def run(tasks, nev: int, results_path: str | None = None, precision: str = "fp64",
+        minres_tol: float = 1e-12, eig_tol: float = 1e-10, gap_tol: float = 1e-5,
+        max_R: int = MAX_R, log=print):
+    """Solve every task; returns the list of per-realization records."""
+    import torch
+
+    done = _done_indices(results_path)
+    todo = [t for t in tasks if t.index not in done]
+    records = []
+    for L in sorted({t.L for t in todo}):
+        group = [t for t in todo if t.L == L]
+        R = widest_batch(L, min(max_R, len(group)))
+        while True:       # narrower batches if the split's tables leave too little LDS
+            basis = Basis(L, tune.best_lo_bits(L, R, precision))
+            mmax = min(basis.n, 3 * nev + 40)
+            try:
+                batch = Batch(basis, R, mmax=mmax, nevmax=nev)
+                break
+            except Exception:
+                if R == 2:
+                    raise
+                R //= 2
+        for start in range(0, len(group), R):
+            chunk = group[start:start + R]
+            real = len(chunk)
+            padded = chunk + [chunk[-1]] * (R - real)
+            t0 = time.perf_counter()
+            sig, esc = [], []
+            for t in padded:
+                lo, hi, sg = sigma_midpoint(basis, t.fields, 1e-12)
+                sig.append(sg)
+                esc.append(max(abs(lo), abs(hi)))
+            t_sigma = time.perf_counter() - t0
+            res = si_lanczos_batched(basis, batch, [t.fields for t in padded], sig, nev, mmax=mmax,
+                                     minres_tol=minres_tol, eig_tol=eig_tol, gap_tol=gap_tol,
+                                     escale=esc, seed=1234 + start, precision=precision)
+            z = twist_expect_batched(basis, batch, res.evecs)
+            torch.cuda.synchronize()
+            t_total = time.perf_counter() - t0
+            for r, t in enumerate(chunk):
+                rec = {
+                    "index": t.index, "L": L, "h": t.h, "sigma": sig[r], "E_min_max_scale": esc[r],
+                    "evals": res.evals[r].tolist(), "resid": res.resid[r].tolist(),
+                    "z_re": np.real(z[r]).tolist(), "z_im": np.imag(z[r]).tolist(),
+                    "steps": int(res.steps[r]), "nconv": int(res.nconv[r]),
+                    "batch_R": R, "batch_seconds": t_total, "sigma_seconds": t_sigma,
+                    "batch_minres_iters": res.minres_iters, "precision": precision,
+                }
+                records.append(rec)
+                if results_path:
+                    with open(results_path, "a") as fh:
+                        fh.write(json.dumps(rec) + "\n")
+            if log:
+                log(f"L={L} batch {start // R} R={R} ({real} real) {t_total:.1f}s "
+                    f"steps={list(res.steps[:real])} nconv={list(res.nconv[:real])}")
+    return records

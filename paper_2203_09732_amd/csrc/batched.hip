@@ -15,9 +15,12 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <numeric>
+#include <string>
+#include <type_traits>
 #include <vector>
 
 namespace mbl {
@@ -721,6 +724,13 @@ struct mbl_batch_s {
   hipEvent_t ev[2] = {nullptr, nullptr};
   size_t part_elems = 0;
   std::vector<double> last_up;      // host copy of the last uploaded (h, c0)
+  // captured MINRES loop (16 iterations) per (vector type, preconditioner)
+  hipGraphExec_t graph[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+  double graph_tol[2][3] = {{0, 0, 0}, {0, 0, 0}};
+  int64_t graph_kmax[2][3] = {{0, 0, 0}, {0, 0, 0}};
+  void* graph_x[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
+  int graph_mode = -1;              // -1: unset (env), 0: eager launches, 1: graphs
+  hipStream_t cap = nullptr;        // capture stream (the caller's may be the null stream)
 };
 
 namespace mbl {
@@ -878,7 +888,60 @@ static mbl_status bminres_core(mbl_basis_s* b, mbl_batch_s* bw, const BatchDev& 
   hipLaunchKernelGGL(k_binit_state, dim3(R), dim3(kWG), 0, s, bw->partials2, G, R, tol, kmax, S);
   MBL_HIP(hipGetLastError());
   const int FG = bflat_grid(n * R);
-  const int64_t kChunkIters = 32;
+  // one iteration k of Alg. 2 for all realizations: five launches
+  auto iteration = [&](int64_t k, hipStream_t st) -> mbl_status {
+    BState* Sin = S + ((k - 1) & 1) * R;
+    BState* Sout = S + (k & 1) * R;
+    MBL_TRY((launch_bapply<T, 1, true>(b, Q, Sin, Qv[k & 1], P, bw->partials1, st)));
+    hipLaunchKernelGGL(k_balpha, dim3(R), dim3(kWG), 0, st, bw->partials1, G, R, Sin);
+    MBL_TRY(launch_bzq<T>(b, Q, precond, Sin, P, Z[k & 1], Z[(k + 1) & 1], Qv[(k + 1) & 1],
+                          bw->partials2, st));
+    hipLaunchKernelGGL(k_bgivens, dim3(R), dim3(kWG), 0, st, bw->partials2, G, R, tol, kmax, Sin,
+                       Sout);
+    hipLaunchKernelGGL((k_bdx<T>), dim3(FG), dim3(kWG), 0, st, n, R, Sout, Sin, Qv[k & 1],
+                       D[(k - 1) & 1], D[k & 1], x);
+    MBL_HIP(hipGetLastError());
+    return MBL_OK;
+  };
+  // The buffers of iteration k depend only on k mod 2, and every kernel reads
+  // its scalars (and the done flags) from device memory, so a block of
+  // kGraphIters iterations is captured once per workspace and replayed; a
+  // replay after convergence is a sequence of no-op launches. tol and kmax
+  // are kernel arguments, so the graph is rebuilt when they change.
+  constexpr int64_t kGraphIters = 16;
+  const int ti = std::is_same<T, float>::value ? 1 : 0;
+  if (bw->graph_mode < 0) {
+    const char* e = getenv("MBL_BATCH_GRAPHS");
+    bw->graph_mode = (e && std::string(e) == "0") ? 0 : 1;
+  }
+  const bool use_graph = bw->graph_mode == 1;
+  hipGraphExec_t& gx = bw->graph[ti][precond];
+  if (use_graph && (bw->graph_tol[ti][precond] != tol || bw->graph_kmax[ti][precond] != kmax ||
+                    bw->graph_x[ti][precond] != (void*)x) && gx) {
+    (void)hipGraphExecDestroy(gx);
+    gx = nullptr;
+  }
+  if (use_graph && !gx) {
+    // captured on the workspace's own stream (nothing runs during capture),
+    // launched on the caller's stream
+    hipGraph_t g = nullptr;
+    MBL_HIP(hipStreamBeginCapture(bw->cap, hipStreamCaptureModeThreadLocal));
+    mbl_status cst = MBL_OK;
+    for (int64_t k = 1; k <= kGraphIters && cst == MBL_OK; ++k) cst = iteration(k, bw->cap);
+    hipError_t ee = hipStreamEndCapture(bw->cap, &g);
+    if (cst != MBL_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return cst;
+    }
+    MBL_HIP(ee);
+    ee = hipGraphInstantiate(&gx, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    MBL_HIP(ee);
+    bw->graph_tol[ti][precond] = tol;
+    bw->graph_kmax[ti][precond] = kmax;
+    bw->graph_x[ti][precond] = (void*)x;
+  }
+  const int64_t kChunkIters = 32;   // a multiple of kGraphIters
   int64_t issued = 0;
   int pending = 0, slot = 0;
   bool done = false;
@@ -892,19 +955,12 @@ static mbl_status bminres_core(mbl_basis_s* b, mbl_batch_s* bw, const BatchDev& 
   };
   while (!done && issued < kmax) {
     const int64_t k_end = std::min(kmax, issued + kChunkIters);
-    for (int64_t k = issued + 1; k <= k_end; ++k) {
-      BState* Sin = S + ((k - 1) & 1) * R;
-      BState* Sout = S + (k & 1) * R;
-      MBL_TRY((launch_bapply<T, 1, true>(b, Q, Sin, Qv[k & 1], P, bw->partials1, s)));
-      hipLaunchKernelGGL(k_balpha, dim3(R), dim3(kWG), 0, s, bw->partials1, G, R, Sin);
-      MBL_TRY(launch_bzq<T>(b, Q, precond, Sin, P, Z[k & 1], Z[(k + 1) & 1], Qv[(k + 1) & 1],
-                            bw->partials2, s));
-      hipLaunchKernelGGL(k_bgivens, dim3(R), dim3(kWG), 0, s, bw->partials2, G, R, tol, kmax, Sin,
-                         Sout);
-      hipLaunchKernelGGL((k_bdx<T>), dim3(FG), dim3(kWG), 0, s, n, R, Sout, Sin, Qv[k & 1],
-                         D[(k - 1) & 1], D[k & 1], x);
+    if (use_graph && k_end - issued == kChunkIters) {
+      for (int64_t rep = 0; rep < kChunkIters / kGraphIters; ++rep)
+        MBL_HIP(hipGraphLaunch(gx, s));
+    } else {
+      for (int64_t k = issued + 1; k <= k_end; ++k) MBL_TRY(iteration(k, s));
     }
-    MBL_HIP(hipGetLastError());
     issued = k_end;
     MBL_HIP(hipMemcpyAsync(bw->h_state + slot * R, S + (issued & 1) * R, sizeof(BState) * R,
                            hipMemcpyDeviceToHost, s));
@@ -1236,6 +1292,10 @@ static void free_batch(mbl_batch_s* w) {
                     w->partials2, w->red, w->scale, w->scale2};
   for (double* p : bufs) (void)hipFree(p);
   (void)hipFree(w->S);
+  for (auto& row : w->graph)
+    for (auto& gx : row)
+      if (gx) (void)hipGraphExecDestroy(gx);
+  if (w->cap) (void)hipStreamDestroy(w->cap);
   if (w->h_state) hipHostFree(w->h_state);
   if (w->h_red) hipHostFree(w->h_red);
   if (w->h_stage) hipHostFree(w->h_stage);
@@ -1309,6 +1369,10 @@ static mbl_status create_batch(mbl_basis_s* b, int R, int mmax, int nevmax, mbl_
       set_error("hipEventCreate failed");
       st = MBL_ERR_HIP;
     }
+  if (st == MBL_OK && hipStreamCreateWithFlags(&w->cap, hipStreamNonBlocking) != hipSuccess) {
+    set_error("hipStreamCreate failed");
+    st = MBL_ERR_HIP;
+  }
   if (st != MBL_OK) {
     free_batch(w);
     return st;
