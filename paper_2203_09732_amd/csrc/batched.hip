@@ -981,6 +981,9 @@ static mbl_status bminres_core(mbl_basis_s* b, mbl_batch_s* bw, const BatchDev& 
   return MBL_OK;
 }
 
+static mbl_status baxpby(mbl_batch_s* bw, int64_t n, const std::vector<double>& a, const double* x,
+                         const std::vector<double>& bb, double* y, hipStream_t s);
+
 // Batched MINRES for (H_r - sigma_r) x_r = b_r from x0 = 0 (fields and shifts
 // already uploaded). FP64, or FP32 inner solves with FP64 residual restarts.
 // active[r] = 0 skips realization r (its x is left at 0).
@@ -1005,29 +1008,57 @@ static mbl_status bminres_run(mbl_basis_s* b, mbl_batch_s* bw, int precision, in
     }
     return MBL_OK;
   }
-  // FP32 inner solves: x64 starts at 0, restart from the FP64 residual
-  const double eta = 1e-6;
+  // FP32 inner solves: x64 starts at 0, restart from the FP64 residual. A
+  // realization whose cycle fails to cut its FP64 residual by kMinCycleGain
+  // leaves the FP32 phase; those are finished together by FP64 MINRES on the
+  // residual (see the single-realization solver for the reasoning).
+  const double eta = 1e-3;
+  const double kMinCycleGain = 10.0;
+  const int max_cycles = 60;
   MBL_HIP(hipMemsetAsync(x, 0, sizeof(double) * n * R, s));
-  std::vector<double> sums(2 * R);
-  for (int cycle = 0; cycle < 200; ++cycle) {
+  std::vector<double> sums(2 * R), prev(R, INFINITY);
+  std::vector<int> fp32_phase(R, 1);
+  for (int cycle = 0;; ++cycle) {
     MBL_TRY(launch_bresidual(b, Q, precond, rhs, x, bw->r64, bw->partials1, s));
     MBL_TRY(breduce_host(bw, bw->partials1, bgrid(b), 2, sums.data(), s));
-    bool any = false;
+    bool any = false, any_fp64 = false;
     double worst = 0;
     for (int r = 0; r < R; ++r) {
       const double rM = std::sqrt(sums[2 * r]);
       phi[r] = rM;
-      const bool go = active[r] && rM >= tol && iters[r] < kmax;
-      sc[r] = go ? 1.0 / rM : 0.0;
-      bw->h_stage[r] = go ? rM : 0.0;
-      any = any || go;
-      if (go) worst = std::max(worst, tol / rM);
       if (!std::isfinite(rM) && active[r]) {
         set_error("non-finite residual in batched FP32-inner MINRES");
         return MBL_ERR_NUMERIC;
       }
+      const bool open = active[r] && rM >= tol && iters[r] < kmax;
+      if (open && fp32_phase[r] && (cycle >= max_cycles || rM > prev[r] / kMinCycleGain))
+        fp32_phase[r] = 0;
+      if (open && !fp32_phase[r]) any_fp64 = true;
+      const bool go = open && fp32_phase[r];
+      sc[r] = go ? 1.0 / rM : 0.0;
+      bw->h_stage[r] = go ? rM : 0.0;
+      if (go) prev[r] = rM;
+      any = any || go;
+      if (go) worst = std::max(worst, tol / rM);
     }
-    if (!any) break;
+    if (!any) {
+      if (any_fp64) {
+        // FP64 finish: A e = r for the realizations that left the FP32 phase
+        for (int r = 0; r < R; ++r)
+          sc[r] = (active[r] && phi[r] >= tol && !fp32_phase[r]) ? 1.0 : 0.0;
+        MBL_HIP(hipMemcpyAsync(bw->scale, sc.data(), sizeof(double) * R, hipMemcpyHostToDevice, s));
+        std::vector<BState> fin;
+        MBL_TRY(bminres_core<double>(b, bw, Q, precond, bw->r64, bw->scale, bw->t64, tol, kmax, s,
+                                     fin));
+        for (int r = 0; r < R; ++r) iters[r] += fin[r].k;
+        std::vector<double> ones(R, 1.0);
+        MBL_TRY(baxpby(bw, n, ones, bw->t64, ones, x, s));
+        MBL_TRY(launch_bresidual(b, Q, precond, rhs, x, bw->r64, bw->partials1, s));
+        MBL_TRY(breduce_host(bw, bw->partials1, bgrid(b), 2, sums.data(), s));
+        for (int r = 0; r < R; ++r) phi[r] = std::sqrt(sums[2 * r]);
+      }
+      break;
+    }
     MBL_HIP(hipMemcpyAsync(bw->scale, sc.data(), sizeof(double) * R, hipMemcpyHostToDevice, s));
     MBL_HIP(hipMemcpyAsync(bw->scale2, bw->h_stage, sizeof(double) * R, hipMemcpyHostToDevice, s));
     const double inner_tol = std::max(eta, 0.5 * worst);

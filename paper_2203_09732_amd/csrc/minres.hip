@@ -602,15 +602,19 @@ mbl_status minres_run(mbl_basis_s* b, const double* h_host, double sigma, const 
     inf.iters = it;
     inf.phi = phi;
   } else {
-    // FP32 inner solves, FP64 residual recomputation and restart.
-    // Each cycle solves A e = r / ||r||_{M^-1} in FP32 to a relative
-    // tolerance eta and updates x += ||r||_{M^-1} e in FP64.
-    const double eta = 1e-6;
-    const int max_restarts = 200;
+    // FP32 inner solves, FP64 residual recomputation and restart. Each cycle
+    // solves A e = r / ||r||_{M^-1} in FP32 to a relative tolerance eta and
+    // updates x += ||r||_{M^-1} e in FP64. FP32 arithmetic bounds what one
+    // cycle can achieve (about u_32 times the condition number), so a cycle
+    // that does not cut the FP64 residual by kMinCycleGain ends the FP32
+    // phase and the solve is finished by FP64 MINRES on the same residual.
+    const double eta = 1e-3;
+    const double kMinCycleGain = 10.0;
+    const int max_restarts = 60;
     int64_t total = 0;
     int restarts = 0;
-    double rM = 0.0;
-    bool first = true;
+    double rM = 0.0, rM_prev = INFINITY;
+    bool first = true, fp64_finish = false;
     for (;;) {
       int np = 0;
       if (first && x0_zero) MBL_HIP(launch_fill(n, 0.0, x, s));
@@ -619,7 +623,16 @@ mbl_status minres_run(mbl_basis_s* b, const double* h_host, double sigma, const 
       MBL_TRY(reduce_to_host(ws, ws->partials1, np, 2, 2, sums, s));
       rM = std::sqrt(sums[0]);
       first = false;
-      if (!(rM >= tol) || total >= kmax || restarts >= max_restarts) break;
+      if (!std::isfinite(rM)) {
+        set_error("non-finite residual in FP32-inner MINRES");
+        return MBL_ERR_NUMERIC;
+      }
+      if (!(rM >= tol) || total >= kmax) break;
+      if (restarts >= max_restarts || rM > rM_prev / kMinCycleGain) {
+        fp64_finish = true;
+        break;
+      }
+      rM_prev = rM;
       const double inner_tol = std::max(eta, 0.5 * tol / rM);
       int64_t it = 0;
       double phi = 0;
@@ -632,14 +645,26 @@ mbl_status minres_run(mbl_basis_s* b, const double* h_host, double sigma, const 
       MBL_HIP(hipGetLastError());
       ++restarts;
     }
+    if (fp64_finish) {
+      // FP64 MINRES on A e = r (r = rhs - A x is in r64), then x += e
+      int64_t it = 0;
+      double phi = 0;
+      double* e64 = ws->t64;
+      mbl_status s3 = minres_core<double>(b, F, ws->r64, 1.0, e64, true, tol, kmax - total,
+                                          precond, ws, &it, &phi, s);
+      if (s3 < 0) return s3;
+      total += it;
+      MBL_HIP(launch_axpby(n, 1.0, e64, 1.0, x, s));
+      int np = 0;
+      MBL_HIP(launch_residual(b, F, precond, rhs, x, ws->r64, ws->partials1, &np, s));
+      double sums[2];
+      MBL_TRY(reduce_to_host(ws, ws->partials1, np, 2, 2, sums, s));
+      rM = std::sqrt(sums[0]);
+    }
     inf.iters = total;
     inf.restarts = restarts;
     inf.phi = rM;
     st = (rM < tol) ? MBL_OK : MBL_WARN_NOCONV;
-    if (!std::isfinite(rM)) {
-      set_error("non-finite residual in FP32-inner MINRES");
-      return MBL_ERR_NUMERIC;
-    }
   }
   // true residual ||b - (H - sigma) x||_2 in FP64
   {
