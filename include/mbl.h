@@ -206,9 +206,12 @@ mbl_status mbl_eig_grad(mbl_basis b, const double* h_host, double E, const doubl
  * sigma_r (sigma_host: R doubles). Batched n-vectors are interleaved:
  * element (i, r) at index i * R + r of an n * R array. R is a power of two,
  * 2 <= R <= 32, and R * 16 * ceil(L/4) doubles of field tables must fit the
- * kernels' 64 KB LDS budget (R = 32 up to L = 24, R = 16 at L = 26);
- * otherwise MBL_ERR_ARG. The basis must use the default lo_bits, and L must
- * be one of 12, 14, ..., 32. The batch workspace holds the recurrence vectors
+ * kernels' 64 KB LDS budget (R = 32 up to L = 24, R = 16 at L = 26), and
+ * n * R * 8 bytes must stay below 2^31 (the kernels address batch vectors
+ * with 32-bit byte offsets); otherwise MBL_ERR_ARG. L must be one of
+ * 12, 14, ..., 32 and the basis's lo_bits one of the splits the library has
+ * batched kernels for (the default split of every such L, and the
+ * alternatives the autotuner measures). The batch workspace holds the recurrence vectors
  * of all realizations and up to mmax Lanczos blocks (n * R * (mmax + 1)
  * doubles). */
 typedef struct mbl_batch_s* mbl_batch;

@@ -10,7 +10,7 @@
 // one chunk per step. Each realization keeps its own fields, shift, MINRES
 // scalars and done flag; per-realization dot products are reduced per
 // workgroup and then by one workgroup per realization, in a fixed order.
-#include "rows.h"
+#include "brows.h"
 
 #include <algorithm>
 #include <chrono>
@@ -25,214 +25,6 @@
 
 namespace mbl {
 
-constexpr int kBWG = 1024;   // threads per workgroup of the batched row kernels
-constexpr int kBMaxR = 32;
-constexpr int kBGrid = 512;  // upper bound on workgroups (partials per realization)
-
-template <typename T> struct Pair;
-template <> struct Pair<double> { using type = double2; };
-template <> struct Pair<float> { using type = float2; };
-
-// Per-realization MINRES state, double-buffered by iteration parity.
-struct BState {
-  double beta_prev, beta, c, s, dhat, eps, phi;
-  double alpha;                 // alpha_k of the current iteration
-  double d_inv_beta, d_delta, d_eps, d_inv_gamma, d_tau;   // d/x update coefficients
-  int64_t k;
-  int32_t done, bad;
-};
-
-struct BatchDev {
-  const double* h;     // R x L fields
-  const double* c0;    // R: L/4 + (1/2) sum h - sigma
-  int R;
-};
-
-// LDS: per-realization nibble tables, then the basis tables.
-__host__ __device__ constexpr size_t blds_bytes(int R, int L, int nlo) {
-  return (size_t)R * (((L + 3) >> 2) * 16) * sizeof(double) + (size_t)R * sizeof(double) +
-         kLdsRed * kBMaxR * sizeof(double) + 2 * sizeof(uint16_t) * ((size_t)1 << nlo);
-}
-
-struct BTables {
-  const double* lut;    // [R][nnib][16]
-  const double* c0;     // [R]
-  double* red;          // [waves][R]
-  const uint16_t* rank;
-  const uint16_t* state;
-};
-
-__device__ __forceinline__ BTables bsetup(const DevBasis& B, const BatchDev& Q, unsigned char* smem) {
-  const int R = Q.R, nnib = (B.L + 3) >> 2;
-  double* lut = reinterpret_cast<double*>(smem);
-  double* c0 = lut + (size_t)R * nnib * 16;
-  double* red = c0 + R;
-  uint16_t* rank = reinterpret_cast<uint16_t*>(red + kLdsRed * kBMaxR);
-  uint16_t* state = rank + (1u << B.nlo);
-  for (int t = threadIdx.x; t < R * nnib * 16; t += blockDim.x) {
-    const int r = t / (nnib * 16), rem = t % (nnib * 16), k = rem >> 4, v = rem & 15;
-    double acc = 0.0;
-    for (int b = 0; b < 4; ++b) {
-      const int site = 4 * k + b;
-      if (site < B.L && ((v >> b) & 1)) acc += Q.h[r * B.L + site];
-    }
-    lut[t] = acc;
-  }
-  for (int t = threadIdx.x; t < R; t += blockDim.x) c0[t] = Q.c0[t];
-  const int words = (1 << B.nlo) >> 1;
-  const uint32_t* gr = reinterpret_cast<const uint32_t*>(B.lo_rank);
-  const uint32_t* gs = reinterpret_cast<const uint32_t*>(B.lo_state);
-  uint32_t* sr = reinterpret_cast<uint32_t*>(rank);
-  uint32_t* ss = reinterpret_cast<uint32_t*>(state);
-  for (int t = threadIdx.x; t < words; t += blockDim.x) {
-    sr[t] = gr[t];
-    ss[t] = gs[t];
-  }
-  return BTables{lut, c0, red, rank, state};
-}
-
-// a_aa - sigma_r for realization r
-template <int L>
-__device__ __forceinline__ double bdiag(const BTables& t, int r, uint32_t a, int nanti) {
-  constexpr int NNIB = (L + 3) >> 2;
-  const double* lr = t.lut + r * NNIB * 16;
-  double fv[NNIB];
-#pragma unroll
-  for (int k = 0; k < NNIB; ++k) fv[k] = lr[(k << 4) + ((a >> (4 * k)) & 15u)];
-  double f = 0.0;
-#pragma unroll
-  for (int k = 0; k < NNIB; ++k) f += fv[k];
-  return t.c0[r] - 0.5 * (double)nanti - f;
-}
-
-template <int L>
-__device__ __forceinline__ int bnanti(uint32_t a) {
-  constexpr uint32_t mask = (L == 32) ? 0xffffffffu : ((1u << L) - 1u);
-  return __popc(a ^ (((a << 1) | (a >> (L - 1))) & mask));
-}
-
-// Off-diagonal sums for the lane's realization pair of one row.
-template <typename T, int L, int NLO>
-__device__ __forceinline__ void boffdiag(const DevBasis& B, const BTables& t,
-                                         const typename Pair<T>::type* __restrict__ x2,
-                                         uint32_t hi, uint32_t lo, uint32_t j, uint32_t block0,
-                                         int PR, int p, double& o0, double& o1) {
-  using T2 = typename Pair<T>::type;
-  constexpr int NHI = L - NLO;
-  constexpr int NLB = NLO - 1 > 0 ? NLO - 1 : 1;
-  constexpr int NHB = NHI - 1 > 0 ? NHI - 1 : 1;
-  const uint32_t hb_bnd = uni(B.hi_off[hi ^ 1u]);
-  const uint32_t hb_wrap = uni(B.hi_off[hi ^ (1u << (NHI - 1))]);
-  uint32_t hb[NHB];
-#pragma unroll
-  for (int b = 0; b + 1 < NHI; ++b) hb[b] = uni(B.hi_off[hi ^ (3u << b)]);
-  uint32_t r[NLB];
-#pragma unroll
-  for (int b = 0; b + 1 < NLO; ++b) r[b] = t.rank[lo ^ (3u << b)];
-  const uint32_t r_bnd = t.rank[lo ^ (1u << (NLO - 1))];
-  const uint32_t r_wrap = t.rank[lo ^ 1u];
-  const T2 zero = {(T)0, (T)0};
-  T2 v[NLB];
-#pragma unroll
-  for (int b = 0; b + 1 < NLO; ++b) {
-    v[b] = zero;
-    if (((lo >> b) ^ (lo >> (b + 1))) & 1u) v[b] = x2[((size_t)block0 + r[b]) * PR + p];
-  }
-  T2 v_bnd = zero;
-  if (((lo >> (NLO - 1)) ^ hi) & 1u) v_bnd = x2[((size_t)hb_bnd + r_bnd) * PR + p];
-  T2 vh[NHB];
-#pragma unroll
-  for (int b = 0; b + 1 < NHI; ++b) {
-    vh[b] = zero;
-    if (((hi >> b) ^ (hi >> (b + 1))) & 1u) vh[b] = x2[((size_t)hb[b] + j) * PR + p];
-  }
-  T2 v_wrap = zero;
-  if (((hi >> (NHI - 1)) ^ lo) & 1u) v_wrap = x2[((size_t)hb_wrap + r_wrap) * PR + p];
-  double a0 = 0.0, a1 = 0.0;
-#pragma unroll
-  for (int b = 0; b + 1 < NLO; ++b) {
-    a0 += (double)v[b].x;
-    a1 += (double)v[b].y;
-  }
-  a0 += (double)v_bnd.x;
-  a1 += (double)v_bnd.y;
-#pragma unroll
-  for (int b = 0; b + 1 < NHI; ++b) {
-    a0 += (double)vh[b].x;
-    a1 += (double)vh[b].y;
-  }
-  a0 += (double)v_wrap.x;
-  a1 += (double)v_wrap.y;
-  o0 = a0;
-  o1 = a1;
-}
-
-// Visit rows: body(row, hi, lo, j, block0, a, p) for lanes with a valid row.
-// The waves of a workgroup cooperate on consecutive chunks: a chunk (up to 64
-// rows) needs PR waves of RPW rows each, so one workgroup step covers
-// wpg / PR chunks. Workgroups of one XCD sweep that XCD's contiguous slice of
-// chunks side by side, so the XCD's live window is about 32 workgroups x 64
-// rows and the rows' low-bond and near high-bond neighbours stay in its L2.
-template <typename Body>
-__device__ __forceinline__ void bfor_rows(const DevBasis& B, const BTables& t, int R, Body body) {
-  const uint32_t PR = (uint32_t)R >> 1, RPW = 64 / PR;
-  const uint32_t lane = threadIdx.x & 63u;
-  const int p = lane % PR;
-  const uint32_t slot = lane / PR;
-  const uint32_t wpg = blockDim.x >> 6;
-  const uint32_t wave = uni(threadIdx.x >> 6);
-  const uint32_t cps = max(1u, wpg / PR);           // chunks per workgroup step
-  const uint32_t my_chunk = wave / PR;              // this wave's chunk in the step
-  const uint32_t my_row0 = (wave % PR) * RPW;       // this wave's first row in the chunk
-  const bool wave_on = my_chunk < cps;
-  const uint32_t G = gridDim.x, nch = (uint32_t)B.nchunks;
-  uint32_t c_lo = 0, c_hi = nch, k = blockIdx.x, per = G;
-  if (G % kXcds == 0) {
-    const uint32_t span = (nch + kXcds - 1) / kXcds;
-    c_lo = min(nch, (blockIdx.x % kXcds) * span);
-    c_hi = min(nch, c_lo + span);
-    k = blockIdx.x / kXcds;
-    per = G / kXcds;
-  }
-  for (uint32_t base = c_lo + k * cps; base < c_hi; base += per * cps) {
-    const uint32_t c = base + my_chunk;
-    if (!wave_on || c >= c_hi) continue;
-    const uint4 ch = B.chunks[c];
-    const uint32_t hi = uni(ch.x), j0 = uni(ch.y), cnt = uni(ch.z), row0 = uni(ch.w);
-    const uint32_t coff = uni(B.lo_coff[B.half - __popc(hi)]);
-    const uint32_t rl = my_row0 + slot;
-    if (rl < cnt) {
-      const uint32_t j = j0 + rl;
-      const uint32_t lo = t.state[coff + j];
-      body(row0 + rl, hi, lo, j, row0 - j0, (hi << B.nlo) | lo, p);
-    }
-  }
-}
-
-// Per-realization block reduction of (acc0, acc1) for pair p; thread r < R of
-// the workgroup ends with the sum for realization r (returned), others 0.
-__device__ __forceinline__ double bblock_sum(double acc0, double acc1, double* red, int R) {
-  const int PR = R >> 1;
-#pragma unroll
-  for (int o = PR; o < 64; o <<= 1) {
-    acc0 += __shfl_xor(acc0, o, 64);
-    acc1 += __shfl_xor(acc1, o, 64);
-  }
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane < PR) {
-    red[wave * R + 2 * lane] = acc0;
-    red[wave * R + 2 * lane + 1] = acc1;
-  }
-  __syncthreads();
-  double s = 0.0;
-  if (threadIdx.x < R) {
-    const int nw = blockDim.x >> 6;
-    for (int w = 0; w < nw; ++w) s += red[w * R + threadIdx.x];
-  }
-  return s;
-}
-
 // ---------------------------------------------------------------------------
 // y = (H_r - sigma_r) x_r for every realization. MODE 1: partial sums of
 // x.y per realization; GUARD: skip realizations whose state is done.
@@ -241,28 +33,35 @@ __global__ __launch_bounds__(kBWG) void k_bapply(DevBasis B, BatchDev Q, const B
                                                  const T* __restrict__ x, T* __restrict__ y,
                                                  double* __restrict__ partials) {
   using T2 = typename Pair<T>::type;
-  const int R = Q.R, PR = R >> 1;
+  const int R = Q.R;
   extern __shared__ __align__(16) unsigned char smem[];
   const BTables t = bsetup(B, Q, smem);
   __syncthreads();
-  const T2* x2 = reinterpret_cast<const T2*>(x);
-  T2* y2 = reinterpret_cast<T2*>(y);
-  const int lane_p = (threadIdx.x & 63) % PR;
+  const uint32_t rs = (uint32_t)t.rsh + (sizeof(T) == 8 ? 3u : 2u);
+  const uint32_t bytes = (uint32_t)B.n << rs;
+  const __amdgpu_buffer_rsrc_t rx = brsrc(x, bytes), ry = brsrc(y, bytes);
+  const int lane_p = (threadIdx.x & 63) % (R >> 1);
   bool live = true;
   if (GUARD) live = !(S[2 * lane_p].done && S[2 * lane_p + 1].done);
   double acc0 = 0.0, acc1 = 0.0;
   if (live) {
-    bfor_rows(B, t, R, [&](uint32_t row, uint32_t hi, uint32_t lo, uint32_t j, uint32_t block0,
+    bfor_rows(B, t, R, [&](uint32_t, uint32_t hi, uint32_t lo, uint32_t j, uint32_t block0,
                            uint32_t a, int p) {
+      BRowAddr ad;
+      ad.rs = rs;
+      ad.lane_off = (uint32_t)p << BIO<T>::kShift;
+      ad.jv = (j << rs) + ad.lane_off;
+      ad.sb = uni(block0) << rs;
       double o0, o1;
-      boffdiag<T, L, NLO>(B, t, x2, hi, lo, j, block0, PR, p, o0, o1);
+      boffdiag<T, L, NLO>(B, t, rx, ad, hi, lo, o0, o1);
       const int na = bnanti<L>(a);
-      const double d0 = bdiag<L>(t, 2 * p, a, na), d1 = bdiag<L>(t, 2 * p + 1, a, na);
-      const T2 xv = x2[(size_t)row * PR + p];
+      double d0, d1;
+      bdiag2<L>(t, p, a, na, d0, d1);
+      const T2 xv = BIO<T>::ld(rx, ad.jv, ad.sb);
       T2 yv;
       yv.x = (T)(d0 * (double)xv.x + 0.5 * o0);
       yv.y = (T)(d1 * (double)xv.y + 0.5 * o1);
-      y2[(size_t)row * PR + p] = yv;
+      BIO<T>::template st<kStoreStream>(yv, ry, ad.jv, ad.sb);
       if (MODE == 1) {
         acc0 += (double)xv.x * (double)yv.x;
         acc1 += (double)xv.y * (double)yv.y;
@@ -283,25 +82,31 @@ __global__ __launch_bounds__(kBWG) void k_bresidual(DevBasis B, BatchDev Q, int 
                                                     const double* __restrict__ x,
                                                     double* __restrict__ res,
                                                     double* __restrict__ partials) {
-  const int R = Q.R, PR = R >> 1;
+  const int R = Q.R;
   extern __shared__ __align__(16) unsigned char smem[];
   const BTables t = bsetup(B, Q, smem);
   __syncthreads();
-  const double2* x2 = reinterpret_cast<const double2*>(x);
-  const double2* b2 = reinterpret_cast<const double2*>(rhs);
-  double2* r2 = reinterpret_cast<double2*>(res);
+  const uint32_t rs = (uint32_t)t.rsh + 3u;
+  const uint32_t bytes = (uint32_t)B.n << rs;
+  const __amdgpu_buffer_rsrc_t rx = brsrc(x, bytes), rb = brsrc(rhs, bytes), rr = brsrc(res, bytes);
   double m0 = 0, m1 = 0, q0 = 0, q1 = 0;
-  bfor_rows(B, t, R, [&](uint32_t row, uint32_t hi, uint32_t lo, uint32_t j, uint32_t block0,
+  bfor_rows(B, t, R, [&](uint32_t, uint32_t hi, uint32_t lo, uint32_t j, uint32_t block0,
                          uint32_t a, int p) {
+    BRowAddr ad;
+    ad.rs = rs;
+    ad.lane_off = (uint32_t)p << 4;
+    ad.jv = (j << rs) + ad.lane_off;
+    ad.sb = uni(block0) << rs;
     double o0, o1;
-    boffdiag<double, L, NLO>(B, t, x2, hi, lo, j, block0, PR, p, o0, o1);
+    boffdiag<double, L, NLO>(B, t, rx, ad, hi, lo, o0, o1);
     const int na = bnanti<L>(a);
-    const double d0 = bdiag<L>(t, 2 * p, a, na), d1 = bdiag<L>(t, 2 * p + 1, a, na);
-    const double2 xv = x2[(size_t)row * PR + p], bv = b2[(size_t)row * PR + p];
+    double d0, d1;
+    bdiag2<L>(t, p, a, na, d0, d1);
+    const double2 xv = BIO<double>::ld(rx, ad.jv, ad.sb), bv = BIO<double>::ld(rb, ad.jv, ad.sb);
     double2 rv;
     rv.x = bv.x - (d0 * xv.x + 0.5 * o0);
     rv.y = bv.y - (d1 * xv.y + 0.5 * o1);
-    r2[(size_t)row * PR + p] = rv;
+    BIO<double>::st<0>(rv, rr, ad.jv, ad.sb);
     m0 += rv.x * rv.x / precond_value(kind, d0, na);
     m1 += rv.y * rv.y / precond_value(kind, d1, na);
     q0 += rv.x * rv.x;
@@ -334,11 +139,14 @@ __global__ __launch_bounds__(kBWG) void k_binit(DevBasis B, BatchDev Q, int kind
   bfor_rows(B, t, R, [&](uint32_t row, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t a, int p) {
     const size_t e = (size_t)row * PR + p;
     const int na = bnanti<L>(a);
-    const double d0v = bdiag<L>(t, 2 * p, a, na), d1v = bdiag<L>(t, 2 * p + 1, a, na);
+    double d0v, d1v;
+    bdiag2<L>(t, p, a, na, d0v, d1v);
     const double2 sv = s2[e];
     T2 zt, qt;
-    zt.x = (T)(scale[2 * p] * sv.x);
-    zt.y = (T)(scale[2 * p + 1] * sv.y);
+    // a zero scale (realization not solved) gives z = 0 whatever src holds
+    const double sc0 = scale[2 * p], sc1 = scale[2 * p + 1];
+    zt.x = (T)(sc0 != 0.0 ? sc0 * sv.x : 0.0);
+    zt.y = (T)(sc1 != 0.0 ? sc1 * sv.y : 0.0);
     qt.x = (T)((double)zt.x / precond_value(kind, d0v, na));
     qt.y = (T)((double)zt.y / precond_value(kind, d1v, na));
     reinterpret_cast<T2*>(z0)[e] = zero;
@@ -381,16 +189,18 @@ __global__ __launch_bounds__(kBWG) void k_bzq(DevBasis B, BatchDev Q, int kind,
       const T2 zv = reinterpret_cast<const T2*>(zk)[e];
       T2 zo = reinterpret_cast<T2*>(zkm1)[e];
       T2 qo = reinterpret_cast<T2*>(qn)[e];
+      double dg0, dg1;
+      bdiag2<L>(t, pp, a, na, dg0, dg1);
       if (live0) {
         const double zn = c10 * (double)pv.x - c20 * (double)zv.x - c30 * (double)zo.x;
         zo.x = (T)zn;
-        qo.x = (T)((double)zo.x / precond_value(kind, bdiag<L>(t, 2 * pp, a, na), na));
+        qo.x = (T)((double)zo.x / precond_value(kind, dg0, na));
         a0 += (double)qo.x * (double)zo.x;
       }
       if (live1) {
         const double zn = c11 * (double)pv.y - c21 * (double)zv.y - c31 * (double)zo.y;
         zo.y = (T)zn;
-        qo.y = (T)((double)zo.y / precond_value(kind, bdiag<L>(t, 2 * pp + 1, a, na), na));
+        qo.y = (T)((double)zo.y / precond_value(kind, dg1, na));
         a1 += (double)qo.y * (double)zo.y;
       }
       reinterpret_cast<T2*>(zkm1)[e] = zo;
@@ -534,8 +344,10 @@ __global__ __launch_bounds__(kWG) void k_badd_scaled(int64_t n, int R, const dou
                                                      double* __restrict__ x) {
   const int64_t total = n * R;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-       i += (int64_t)gridDim.x * blockDim.x)
-    x[i] += scale[i & (R - 1)] * (double)e[i];
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double sc = scale[i & (R - 1)];
+    if (sc != 0.0) x[i] += sc * (double)e[i];   // a zero scale leaves x untouched
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -606,7 +418,11 @@ __global__ __launch_bounds__(kWG) void k_baxpby(int64_t n, int R, const double* 
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int r = (int)(e % R);
-    y[e] = a[r] * x[e] + b[r] * y[e];
+    // BLAS convention: a zero coefficient does not read its operand, so
+    // stale or unset entries of x or y never reach the result
+    const double ar = a[r], br = b[r];
+    const double ax = ar != 0.0 ? ar * x[e] : 0.0;
+    y[e] = br != 0.0 ? ax + br * y[e] : ax;
   }
 }
 
@@ -735,10 +551,28 @@ struct mbl_batch_s {
 
 namespace mbl {
 
+// Workgroups of the batched row kernels: one 1024-thread workgroup per
+// compute unit (measured: a second resident workgroup per CU slows the
+// gather-bound apply), fewer for small bases, whole XCD slices once large.
+static int device_cus(int device) {
+  static int cached[64] = {0};
+  if (device < 0 || device >= 64) return 256;
+  if (cached[device] == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
+        v <= 0) {
+      (void)hipGetLastError();
+      v = 256;
+    }
+    cached[device] = v;
+  }
+  return cached[device];
+}
+
 static int bgrid(const mbl_basis_s* b) {
   int g = (b->nchunks + (kBWG / 64) - 1) / (kBWG / 64);
-  g = std::max(1, std::min(g, kBGrid));
-  return g >= 64 ? (g / 8) * 8 : g;   // whole XCD slices once the grid is large
+  g = std::max(1, std::min({g, kBGrid, device_cus(b->device)}));
+  return g >= 64 ? (g / 8) * 8 : g;
 }
 
 static bool batched_split_supported(const mbl_basis_s* b) {
@@ -1428,6 +1262,8 @@ mbl_status mbl_batch_create(mbl_basis b, int R, int mmax, int nevmax, mbl_batch*
           "need 0 <= nevmax <= mmax <= 1000");
   MBL_ARG(batched_split_supported(b), "batched form needs the library's default lo_bits for L");
   MBL_ARG(blds_bytes(R, b->L, b->nlo) <= 65536, "R too large for this L (LDS)");
+  MBL_ARG((uint64_t)b->n * (uint64_t)R * sizeof(double) < ((uint64_t)1 << 31),
+          "n * R * 8 bytes must stay below 2^31 (32-bit buffer offsets); use a smaller R");
   return create_batch(b, R, mmax, nevmax, out);
 }
 

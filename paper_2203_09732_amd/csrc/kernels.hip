@@ -195,8 +195,11 @@ __global__ __launch_bounds__(kWG) void k_reduce(const double* __restrict__ parti
 __global__ __launch_bounds__(kWG) void k_axpby(int64_t n, double a, const double* __restrict__ x,
                                                double b, double* __restrict__ y) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
-    y[i] = a * x[i] + b * y[i];
+       i += (int64_t)gridDim.x * blockDim.x) {
+    // BLAS convention: a zero coefficient does not read its operand
+    const double ax = a != 0.0 ? a * x[i] : 0.0;
+    y[i] = b != 0.0 ? ax + b * y[i] : ax;
+  }
 }
 
 __global__ __launch_bounds__(kWG) void k_scale_copy(int64_t n, double a, const double* __restrict__ x,

@@ -143,3 +143,27 @@ def test_si_lanczos_batched_parity(gpu, torch, precision):
         assert np.all(np.abs(z[r] - zr) <= 2 * dpsi + 1e-12)
         rr = lanczos.eigen_residuals(Hs[r], res.evals[r], Ur)
         assert np.allclose(res.resid[r], rr, rtol=1e-6, atol=1e-14)
+
+
+def test_si_lanczos_batched_frozen_realization_with_poisoned_memory(gpu, torch):
+    """Realizations that converge early are frozen with zero coefficients
+    while the others go on; their later Lanczos columns are never computed.
+    Device memory filled with NaN and released just before the batch is
+    created must not reach any result (a zero coefficient reads nothing)."""
+    say("si_lanczos batched frozen realization, NaN-poisoned memory")
+    L, R, nev = 12, 2, 2
+    fields = [disorder_fields(L, 2.0, 100), disorder_fields(L, 4.0, 102)]
+    b = gpu.Basis(L)
+    sig = [gpu.sigma_midpoint(b, f, 1e-12)[2] for f in fields]
+    junk = torch.full((64 << 20,), float("nan"), dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    del junk
+    torch.cuda.empty_cache()
+    bt = gpu.Batch(b, R, mmax=46, nevmax=nev)
+    res = gpu.si_lanczos_batched(b, bt, fields, sig, nev, mmax=46, escale=[15.0, 15.0], seed=1234)
+    assert res.status == 0 and np.all(res.nconv == nev)
+    assert res.steps[0] != res.steps[1]   # one realization was frozen while the other ran
+    for r in range(R):
+        H = model.hamiltonian_dense(L, fields[r])
+        E, _ = lanczos.eigenpairs_dense(H, sig[r], nev)
+        assert np.all(np.abs(res.evals[r] - E) / np.maximum(np.abs(E), 1) <= 1e-10)
