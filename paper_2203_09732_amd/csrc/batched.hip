@@ -294,36 +294,69 @@ __global__ void k_bgivens(const double* __restrict__ partials, int G, int R, dou
   }
 }
 
-// d_k = (q_k / beta_k - delta_k d_{k-1} - eps_k d_{k-2}) / gamma_k, x += tau_k d_k
-// for the realizations that took step k (Sk is the state after step k; a
-// realization done before step k has d_tau = 0 and is left untouched).
+// The d/x update of Alg. 2 for kDxGroup consecutive iterations in one pass:
+// each element walks d_k = (q_k / beta_k - delta_k d_{k-1} - eps_k d_{k-2}) /
+// gamma_k, x += tau_k d_k for k = k_first .. k_first + count - 1 with the same
+// per-element arithmetic as one update per iteration, reading q_k from the
+// ring and the coefficients from the ring of states, and stores only the last
+// two d's and x. Iterations in which a realization was already done are
+// skipped for it.
+constexpr int kDxGroup = 4;
+constexpr int kRing = 8;   // q vectors and iteration states kept; a divisor of the graph length
+
 template <typename T>
-__global__ __launch_bounds__(kWG) void k_bdx(int64_t n, int R, const BState* __restrict__ Sk,
-                                             const BState* __restrict__ Sprev,
-                                             const T* __restrict__ qk, const T* __restrict__ dkm1,
-                                             T* __restrict__ dkm2, T* __restrict__ x) {
-  __shared__ double co[kBMaxR][5];
-  __shared__ int act[kBMaxR];
-  if (threadIdx.x < R) {
-    const BState s = Sk[threadIdx.x];
-    co[threadIdx.x][0] = s.d_inv_beta;
-    co[threadIdx.x][1] = s.d_delta;
-    co[threadIdx.x][2] = s.d_eps;
-    co[threadIdx.x][3] = s.d_inv_gamma;
-    co[threadIdx.x][4] = s.d_tau;
-    act[threadIdx.x] = !Sprev[threadIdx.x].done;
+struct QRing {
+  const T* q[kRing];
+};
+
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_bdx_group(int64_t n, int R, const BState* __restrict__ S,
+                                                   QRing<T> Qr, int64_t k_first, int count,
+                                                   T* __restrict__ d_a, T* __restrict__ d_b,
+                                                   T* __restrict__ x) {
+  // d_a holds d_{k} for even k, d_b for odd k
+  __shared__ double co[kDxGroup][kBMaxR][5];
+  __shared__ int act[kDxGroup][kBMaxR];
+  for (int t = threadIdx.x; t < count * R; t += blockDim.x) {
+    const int j = t / R, r = t % R;
+    const int64_t k = k_first + j;
+    const BState sk = S[(size_t)(k % kRing) * R + r];
+    co[j][r][0] = sk.d_inv_beta;
+    co[j][r][1] = sk.d_delta;
+    co[j][r][2] = sk.d_eps;
+    co[j][r][3] = sk.d_inv_gamma;
+    co[j][r][4] = sk.d_tau;
+    act[j][r] = !S[(size_t)((k - 1) % kRing) * R + r].done;
   }
   __syncthreads();
+  T* dk1 = ((k_first - 1) & 1) ? d_b : d_a;   // d_{k_first - 1}
+  T* dk2 = ((k_first - 1) & 1) ? d_a : d_b;   // d_{k_first - 2}
   const int64_t total = n * R;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int r = (int)(e & (R - 1));
-    if (!act[r]) continue;
-    const double d = ((double)qk[e] * co[r][0] - co[r][1] * (double)dkm1[e] -
-                      co[r][2] * (double)dkm2[e]) * co[r][3];
-    const T dt = (T)d;
-    dkm2[e] = dt;
-    x[e] = (T)((double)x[e] + co[r][4] * (double)dt);
+    if (!act[0][r]) continue;
+    double dm1 = (double)dk1[e], dm2 = (double)dk2[e];
+    T xv = x[e];
+    int last = -1;
+#pragma unroll
+    for (int j = 0; j < kDxGroup; ++j) {
+      if (j >= count || !act[j][r]) break;
+      const int64_t k = k_first + j;
+      const double d = ((double)Qr.q[k % kRing][e] * co[j][r][0] - co[j][r][1] * dm1 -
+                        co[j][r][2] * dm2) * co[j][r][3];
+      const T dt = (T)d;
+      xv = (T)((double)xv + co[j][r][4] * (double)dt);
+      dm2 = dm1;
+      dm1 = (double)dt;
+      last = j;
+    }
+    if (last >= 0) {
+      const int64_t kl = k_first + last;            // d_kl in dm1, d_{kl-1} in dm2
+      ((kl & 1) ? d_b : d_a)[e] = (T)dm1;
+      ((kl & 1) ? d_a : d_b)[e] = (T)dm2;
+      x[e] = xv;
+    }
   }
 }
 
@@ -516,9 +549,9 @@ struct mbl_batch_s {
   int64_t n = 0, bytes = 0;
   double* h = nullptr;       // R * L
   double* c0 = nullptr;      // R
-  mbl::BState* S = nullptr;  // 2 * R
+  mbl::BState* S = nullptr;  // kRing * R
   double* z[2] = {nullptr, nullptr};
-  double* q[2] = {nullptr, nullptr};
+  double* q[mbl::kRing] = {};
   double* d[2] = {nullptr, nullptr};
   double* p = nullptr;
   double* e = nullptr;
@@ -712,32 +745,42 @@ static mbl_status bminres_core(mbl_basis_s* b, mbl_batch_s* bw, const BatchDev& 
   const int R = bw->R;
   const int64_t n = b->n;
   T* Z[2] = {(T*)bw->z[0], (T*)bw->z[1]};
-  T* Qv[2] = {(T*)bw->q[0], (T*)bw->q[1]};
+  T* Qv[kRing];
+  QRing<T> qr;
+  for (int i = 0; i < kRing; ++i) qr.q[i] = Qv[i] = (T*)bw->q[i];
   T* D[2] = {(T*)bw->d[0], (T*)bw->d[1]};
   T* P = (T*)bw->p;
   const int G = bgrid(b);
   BState* S = bw->S;
+  // z_0 in Z[0], z_1 in Z[1], q_1 in Qv[1], d_0 in D[0], d_{-1} in D[1]
   MBL_TRY(launch_binit<T>(b, Q, precond, src, scale_dev, Z[0], Z[1], Qv[1], D[0], D[1], x,
                           bw->partials2, s));
   hipLaunchKernelGGL(k_binit_state, dim3(R), dim3(kWG), 0, s, bw->partials2, G, R, tol, kmax, S);
   MBL_HIP(hipGetLastError());
   const int FG = bflat_grid(n * R);
-  // one iteration k of Alg. 2 for all realizations: five launches
-  auto iteration = [&](int64_t k, hipStream_t st) -> mbl_status {
-    BState* Sin = S + ((k - 1) & 1) * R;
-    BState* Sout = S + (k & 1) * R;
-    MBL_TRY((launch_bapply<T, 1, true>(b, Q, Sin, Qv[k & 1], P, bw->partials1, st)));
-    hipLaunchKernelGGL(k_balpha, dim3(R), dim3(kWG), 0, st, bw->partials1, G, R, Sin);
-    MBL_TRY(launch_bzq<T>(b, Q, precond, Sin, P, Z[k & 1], Z[(k + 1) & 1], Qv[(k + 1) & 1],
-                          bw->partials2, st));
-    hipLaunchKernelGGL(k_bgivens, dim3(R), dim3(kWG), 0, st, bw->partials2, G, R, tol, kmax, Sin,
-                       Sout);
-    hipLaunchKernelGGL((k_bdx<T>), dim3(FG), dim3(kWG), 0, st, n, R, Sout, Sin, Qv[k & 1],
-                       D[(k - 1) & 1], D[k & 1], x);
+  // d/x updates of iterations k_first .. k_first + count - 1
+  auto dx_group = [&](int64_t k_first, int count, hipStream_t st) -> mbl_status {
+    hipLaunchKernelGGL((k_bdx_group<T>), dim3(FG), dim3(kWG), 0, st, n, R, S, qr, k_first, count,
+                       D[0], D[1], x);
     MBL_HIP(hipGetLastError());
     return MBL_OK;
   };
-  // The buffers of iteration k depend only on k mod 2, and every kernel reads
+  // one iteration k of Alg. 2 for all realizations; the d/x update follows
+  // every kDxGroup iterations
+  auto iteration = [&](int64_t k, hipStream_t st) -> mbl_status {
+    BState* Sin = S + ((k - 1) % kRing) * R;
+    BState* Sout = S + (k % kRing) * R;
+    MBL_TRY((launch_bapply<T, 1, true>(b, Q, Sin, Qv[k % kRing], P, bw->partials1, st)));
+    hipLaunchKernelGGL(k_balpha, dim3(R), dim3(kWG), 0, st, bw->partials1, G, R, Sin);
+    MBL_TRY(launch_bzq<T>(b, Q, precond, Sin, P, Z[k & 1], Z[(k + 1) & 1], Qv[(k + 1) % kRing],
+                          bw->partials2, st));
+    hipLaunchKernelGGL(k_bgivens, dim3(R), dim3(kWG), 0, st, bw->partials2, G, R, tol, kmax, Sin,
+                       Sout);
+    MBL_HIP(hipGetLastError());
+    if (k % kDxGroup == 0) MBL_TRY(dx_group(k - kDxGroup + 1, kDxGroup, st));
+    return MBL_OK;
+  };
+  // The buffers of iteration k depend only on k mod kRing, and every kernel reads
   // its scalars (and the done flags) from device memory, so a block of
   // kGraphIters iterations is captured once per workspace and replayed; a
   // replay after convergence is a sequence of no-op launches. tol and kmax
@@ -796,7 +839,9 @@ static mbl_status bminres_core(mbl_basis_s* b, mbl_batch_s* bw, const BatchDev& 
       for (int64_t k = issued + 1; k <= k_end; ++k) MBL_TRY(iteration(k, s));
     }
     issued = k_end;
-    MBL_HIP(hipMemcpyAsync(bw->h_state + slot * R, S + (issued & 1) * R, sizeof(BState) * R,
+    if (issued % kDxGroup != 0)   // only at kmax: the d/x update of the last iterations
+      MBL_TRY(dx_group(issued - issued % kDxGroup + 1, (int)(issued % kDxGroup), s));
+    MBL_HIP(hipMemcpyAsync(bw->h_state + slot * R, S + (issued % kRing) * R, sizeof(BState) * R,
                            hipMemcpyDeviceToHost, s));
     MBL_HIP(hipEventRecord(bw->ev[slot], s));
     ++pending;
@@ -1152,10 +1197,11 @@ static mbl_status bsi_lanczos_run(mbl_basis_s* b, mbl_batch_s* bw, const double*
 
 static void free_batch(mbl_batch_s* w) {
   if (!w) return;
-  double* bufs[] = {w->h, w->c0, w->z[0], w->z[1], w->q[0], w->q[1], w->d[0], w->d[1], w->p,
+  double* bufs[] = {w->h, w->c0, w->z[0], w->z[1], w->d[0], w->d[1], w->p,
                     w->e, w->r64, w->t64, w->w, w->x, w->V, w->coef, w->ycoef, w->partials1,
                     w->partials2, w->red, w->scale, w->scale2};
   for (double* p : bufs) (void)hipFree(p);
+  for (double* p : w->q) (void)hipFree(p);
   (void)hipFree(w->S);
   for (auto& row : w->graph)
     for (auto& gx : row)
@@ -1196,9 +1242,9 @@ static mbl_status create_batch(mbl_basis_s* b, int R, int mmax, int nevmax, mbl_
   A(&w->c0, R);
   for (int i = 0; i < 2; ++i) {
     A(&w->z[i], NR);
-    A(&w->q[i], NR);
     A(&w->d[i], NR);
   }
+  for (int i = 0; i < kRing; ++i) A(&w->q[i], NR);
   A(&w->p, NR);
   A(&w->e, NR);
   A(&w->r64, NR);
@@ -1214,7 +1260,7 @@ static mbl_status create_batch(mbl_basis_s* b, int R, int mmax, int nevmax, mbl_
   A(&w->red, (size_t)std::max(R * 64, (mmax + 1) * R));
   A(&w->scale, R);
   A(&w->scale2, R);
-  if (st == MBL_OK && hipMalloc((void**)&w->S, sizeof(BState) * 2 * R) != hipSuccess) {
+  if (st == MBL_OK && hipMalloc((void**)&w->S, sizeof(BState) * kRing * R) != hipSuccess) {
     (void)hipGetLastError();
     set_error("device allocation failed (batched state)");
     st = MBL_ERR_NOMEM;
