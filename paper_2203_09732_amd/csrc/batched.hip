@@ -61,7 +61,10 @@ __global__ __launch_bounds__(kBWG) void k_bapply(DevBasis B, BatchDev Q, const B
       T2 yv;
       yv.x = (T)(d0 * (double)xv.x + 0.5 * o0);
       yv.y = (T)(d1 * (double)xv.y + 0.5 * o1);
-      BIO<T>::template st<kStoreStream>(yv, ry, ad.jv, ad.sb);
+      if (MODE == 0)
+        BIO<T>::template st<kStoreStream>(yv, ry, ad.jv, ad.sb);
+      else   // the MINRES product is read back by the next kernel
+        BIO<T>::template st<0>(yv, ry, ad.jv, ad.sb);
       if (MODE == 1) {
         acc0 += (double)xv.x * (double)yv.x;
         acc1 += (double)xv.y * (double)yv.y;
@@ -162,7 +165,9 @@ __global__ __launch_bounds__(kBWG) void k_binit(DevBasis B, BatchDev Q, int kind
   if (threadIdx.x < R) partials[(size_t)blockIdx.x * R + threadIdx.x] = s;
 }
 
-// z_{k+1}, q_{k+1} and partial sums of q_{k+1} . z_{k+1}, for live realizations.
+// z_{k+1}, q_{k+1} and partial sums of q_{k+1} . z_{k+1}, for live
+// realizations. A realization that is done gets z_{k+1} = q_{k+1} = 0 (never
+// read by its own recurrence again), so the old q_{k+1} slot is not read.
 template <typename T, int L>
 __global__ __launch_bounds__(kBWG) void k_bzq(DevBasis B, BatchDev Q, int kind,
                                               const BState* __restrict__ S,
@@ -174,6 +179,10 @@ __global__ __launch_bounds__(kBWG) void k_bzq(DevBasis B, BatchDev Q, int kind,
   extern __shared__ __align__(16) unsigned char smem[];
   const BTables t = bsetup(B, Q, smem);
   __syncthreads();
+  const uint32_t rs = (uint32_t)t.rsh + (sizeof(T) == 8 ? 3u : 2u);
+  const uint32_t bytes = (uint32_t)B.n << rs;
+  const __amdgpu_buffer_rsrc_t rp = brsrc(p, bytes), rz = brsrc(zk, bytes),
+                               rzo = brsrc(zkm1, bytes), rq = brsrc(qn, bytes);
   const int lp = (threadIdx.x & 63) % PR;
   const BState s0 = S[2 * lp], s1 = S[2 * lp + 1];
   const bool live0 = !s0.done, live1 = !s1.done;
@@ -181,30 +190,31 @@ __global__ __launch_bounds__(kBWG) void k_bzq(DevBasis B, BatchDev Q, int kind,
   const double c11 = 1.0 / s1.beta, c21 = s1.alpha / s1.beta, c31 = s1.beta / s1.beta_prev;
   double a0 = 0, a1 = 0;
   if (live0 || live1) {
-    bfor_rows(B, t, R, [&](uint32_t row, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t a,
+    bfor_rows(B, t, R, [&](uint32_t, uint32_t, uint32_t, uint32_t j, uint32_t block0, uint32_t a,
                            int pp) {
-      const size_t e = (size_t)row * PR + pp;
+      const uint32_t jv = (j << rs) + ((uint32_t)pp << BIO<T>::kShift);
+      const uint32_t sb = uni(block0) << rs;
       const int na = bnanti<L>(a);
-      const T2 pv = reinterpret_cast<const T2*>(p)[e];
-      const T2 zv = reinterpret_cast<const T2*>(zk)[e];
-      T2 zo = reinterpret_cast<T2*>(zkm1)[e];
-      T2 qo = reinterpret_cast<T2*>(qn)[e];
+      const T2 pv = BIO<T>::ld(rp, jv, sb);
+      const T2 zv = BIO<T>::ld(rz, jv, sb);
+      const T2 zm = BIO<T>::ld(rzo, jv, sb);
       double dg0, dg1;
       bdiag2<L>(t, pp, a, na, dg0, dg1);
+      T2 zo = {(T)0, (T)0}, qo = {(T)0, (T)0};
       if (live0) {
-        const double zn = c10 * (double)pv.x - c20 * (double)zv.x - c30 * (double)zo.x;
+        const double zn = c10 * (double)pv.x - c20 * (double)zv.x - c30 * (double)zm.x;
         zo.x = (T)zn;
         qo.x = (T)((double)zo.x / precond_value(kind, dg0, na));
         a0 += (double)qo.x * (double)zo.x;
       }
       if (live1) {
-        const double zn = c11 * (double)pv.y - c21 * (double)zv.y - c31 * (double)zo.y;
+        const double zn = c11 * (double)pv.y - c21 * (double)zv.y - c31 * (double)zm.y;
         zo.y = (T)zn;
         qo.y = (T)((double)zo.y / precond_value(kind, dg1, na));
         a1 += (double)qo.y * (double)zo.y;
       }
-      reinterpret_cast<T2*>(zkm1)[e] = zo;
-      reinterpret_cast<T2*>(qn)[e] = qo;
+      BIO<T>::template st<0>(zo, rzo, jv, sb);
+      BIO<T>::template st<0>(qo, rq, jv, sb);
     });
   }
   const double s = bblock_sum(a0, a1, t.red, R);
