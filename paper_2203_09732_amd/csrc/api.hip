@@ -172,7 +172,7 @@ static mbl_status create_ws(mbl_basis_s* b, int mmax, int precision, bool minres
   A(&w->partials3, (size_t)kMaxPartials);
   A(&w->red_out, 256);
   A(&w->state, 2);
-  A(&w->sync, 4);
+  A(&w->sync, kSyncWords);
   if (st == MBL_OK) {
     if (hipHostMalloc((void**)&w->h_state, 4 * sizeof(MinresState)) != hipSuccess ||
         hipHostMalloc((void**)&w->h_red, 256 * sizeof(double)) != hipSuccess) {

@@ -83,6 +83,24 @@ struct Defl {
   int P = 0;
 };
 
+// Words of the grid-barrier block of a workspace (device, zeroed before a
+// cooperative launch): 64-bit arrival counter, 64-bit release generation,
+// the published sum (a double), the failure flag.
+constexpr int kSyncWords = 8;
+constexpr int kSyncFailWord = 6;
+struct GridSync {
+  unsigned long long* count;
+  unsigned long long* gen;
+  unsigned long long* result;
+  int* fail;
+};
+inline GridSync grid_sync(unsigned int* words) {
+  return GridSync{reinterpret_cast<unsigned long long*>(words),
+                  reinterpret_cast<unsigned long long*>(words + 2),
+                  reinterpret_cast<unsigned long long*>(words + 4),
+                  reinterpret_cast<int*>(words + kSyncFailWord)};
+}
+
 // MINRES scalar state after iteration k (two slots, k & 1).
 struct MinresState {
   double beta_prev, beta, c, s, dhat, eps, phi;
@@ -135,7 +153,7 @@ struct mbl_workspace_s {
   double* partials3 = nullptr;   // kMaxPartials
   double* red_out = nullptr;     // 256 doubles
   mbl::MinresState* state = nullptr;  // 2 slots
-  unsigned int* sync = nullptr;       // grid barrier counter + failure flag
+  unsigned int* sync = nullptr;       // kSyncWords: grid barrier words (GridSync)
   mbl::MinresState* h_state = nullptr;  // pinned host, 4 slots
   double* h_red = nullptr;              // pinned host, 256 doubles
   hipEvent_t ev[2] = {nullptr, nullptr};
