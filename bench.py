@@ -85,6 +85,8 @@ def parse():
     ap.add_argument("--eig-batched-mixed", action="store_true",
                     help="also time the lockstep FP32-inner eigen leg (minutes)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--largest", action="store_true",
+                    help="also measure the L=26 workload (memory, apply, MINRES per iteration)")
     ap.add_argument("--minres-iters", type=int, default=1000)
     ap.add_argument("--profile-run", action="store_true",
                     help="counter pass: 10 batched applies and 10 plain copies of the same size")
@@ -168,6 +170,87 @@ def eig_leg(mbl, torch, L, nev, R, batched_mixed=False):
                                   "steps_max": int(resb.steps.max()),
                                   "minres_iters": int(resb.minres_iters)}
     out["unit"] = "s per converged eigenpair"
+    return out
+
+
+def largest_leg(mbl, torch, steps=20):
+    """The largest single-GPU workload (L=26, n = 10 400 600, h = 3.8, seed 0):
+    device memory of a workspace against the linear model, apply throughput
+    (one realization per launch, and 16 in lockstep), MINRES time per
+    iteration in both precisions. Bounded: no converged eigenpair."""
+    from workloads import WORKLOADS, disorder_fields
+    cfg = WORKLOADS["largest_L26"]
+    L = cfg["L"]
+    h = disorder_fields(L, cfg["h"], cfg["seeds"][0])
+    b = mbl.Basis(L)
+    n = b.n
+    out = {"L": L, "n": n, "h": cfg["h"], "lo_bits": b.lo_bits}
+    free0 = torch.cuda.mem_get_info()[0]
+    ws = mbl.Workspace(b, 70)
+    torch.cuda.synchronize()
+    free1 = torch.cuda.mem_get_info()[0]
+    out["workspace_mmax70_bytes"] = ws.bytes
+    out["device_bytes_taken"] = int(free0 - free1)
+    out["linear_model_bytes_8n(12+71)"] = 8 * n * (12 + 71)
+    out["paper_model_bytes_8n(9+m)_m70"] = 8 * n * (9 + 70)
+    t = time.perf_counter()
+    lo, hi, sigma = mbl.sigma_midpoint(b, h, 1e-10)
+    out["sigma"] = sigma
+    out["sigma_seconds"] = round(time.perf_counter() - t, 3)
+    progress(f"largest L=26: sigma {sigma:.6f} in {out['sigma_seconds']} s")
+    g = torch.Generator(device="cuda").manual_seed(2)
+    pairs = [(torch.randn(n, dtype=torch.float64, device="cuda", generator=g),
+              torch.empty(n, dtype=torch.float64, device="cuda")) for _ in range(4)]
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for x, y in pairs:
+        mbl.apply_H(b, h, sigma, x, y)
+    e0.record(stream)
+    for i in range(steps):
+        x, y = pairs[i % 4]
+        mbl.apply_H(b, h, sigma, x, y)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / steps
+    out["apply_single"] = {"us": round(us, 2), "GBps": round(16.0 * n / us / 1e3, 1)}
+    progress(f"largest L=26: single apply {us:.1f} us")
+    del pairs
+    R = 16
+    bt = mbl.Batch(b, R)
+    fields = [disorder_fields(L, cfg["h"], s) for s in range(R)]
+    sig = [sigma] * R
+    X = torch.randn((n, R), dtype=torch.float64, device="cuda", generator=g)
+    Y = torch.empty_like(X)
+    mbl.apply_H_batched(b, bt, fields, sig, X, Y)
+    e0.record(stream)
+    for _ in range(max(2, steps // 4)):
+        mbl.apply_H_batched(b, bt, fields, sig, X, Y)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / max(2, steps // 4)
+    out["apply_batched_R16"] = {"us": round(us, 2), "GBps": round(16.0 * n * R / us / 1e3, 1)}
+    progress(f"largest L=26: batched R=16 apply {us:.1f} us")
+    rhs = (X[:, 0] / X[:, 0].norm()).contiguous()
+    for prec in ("fp64", "fp32_inner"):
+        x = torch.zeros_like(rhs)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, info = mbl.minres_solve(b, h, sigma, rhs, x, tol=1e-300, kmax=200, precision=prec, ws=ws)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        out["minres_single_" + prec] = {"iters": int(info.iters),
+                                        "us_per_iter": round(dt / max(info.iters, 1) * 1e6, 2)}
+        progress(f"largest L=26: minres single {prec} {dt / max(info.iters, 1) * 1e6:.1f} us/iter")
+    Bn = (X / X.norm(dim=0, keepdim=True)).contiguous()
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, its, _, _ = mbl.minres_solve_batched(b, bt, fields, sig, Bn, tol=1e-300, kmax=32)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    it = int(its.max())
+    out["minres_batched_R16_fp64"] = {"iters": it, "us_per_iter": round(dt / it * 1e6, 1),
+                                      "us_per_realization_iter": round(dt / it / R * 1e6, 2)}
+    progress(f"largest L=26: minres batched R=16 {dt / it * 1e6:.1f} us/iter")
     return out
 
 
@@ -345,6 +428,8 @@ def main():
         out["sec_per_eigenpair"] = eig_leg(mbl, torch, args.eig_L, args.eig_nev, args.eig_R,
                                            args.eig_batched_mixed)
         out["sec_per_eigenpair_L22_projection"] = l22_projection(minres)
+    if args.largest:
+        out["largest_L26"] = largest_leg(mbl, torch)
     if not args.no_cpu:
         progress("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(fields, sigmas, L)

@@ -86,3 +86,75 @@ def test_autograd_eigpair(gpu, torch):
     ref = 0.3 * adjoint.hellmann_feynman(L, psi) + 2.0 * adjoint.dz2_dh(L, psi, dpsi)
     assert abs(E.item() - E_sel[1]) <= 1e-10
     assert np.abs(ht.grad.numpy() - ref).max() <= 1e-7 * max(1.0, np.abs(ref).max())
+
+
+def _inverse_iteration(gpu, torch, b, h, E, psi, steps=3, tol=1e-9):
+    """Eigenvector of H(h) nearest E by inverse iteration from psi: each step
+    solves (H - E) y = v with MINRES and normalises (the perturbed eigenvalue
+    is within ~1e-7 of E, so each step shrinks the other components by
+    ~1e-7 / gap)."""
+    v = psi / torch.linalg.norm(psi)
+    for _ in range(steps):
+        y, _info = gpu.minres_solve(b, h, E, v.contiguous(), tol=tol, kmax=40 * b.n)
+        v = y / torch.linalg.norm(y)
+    if float(torch.dot(v, psi)) < 0:
+        v = -v
+    return v
+
+
+def _fd_subset(gpu, torch, L, seeds, sites, delta=1e-7):
+    """Adjoint derivatives of the eigenpair nearest sigma against central
+    finite differences, the perturbed eigenpairs found by inverse iteration
+    seeded from psi with shift E (Rayleigh quotient for E', twist of psi' for
+    z'). Returns the largest deviations."""
+    worst_E, worst_z = 0.0, 0.0
+    for seed in seeds:
+        h = disorder_fields(L, 3.0, seed)
+        b = gpu.Basis(L)
+        lo, hi, sg = gpu.sigma_midpoint(b, h, 1e-12)
+        res = gpu.si_lanczos(b, h, sg, 2, escale=max(abs(lo), abs(hi)),
+                             v0=torch.as_tensor(start_vector(b.n, seed), device="cuda"))
+        assert res.nconv == 2
+        t = int(np.argmin(np.abs(res.evals - sg)))
+        E = res.evals[t]
+        psi = res.evecs[:, t].contiguous()
+        gap = float(np.min(np.abs(np.delete(res.evals, t) - E)))
+        dE, dz2, z, info = gpu.eig_grad(b, h, E, psi, tol=1e-12)
+        assert abs(dE.sum()) <= 1e-10 and abs(dz2.sum()) <= 1e-7 * max(1.0, np.abs(dz2).max())
+        for j in sites:
+            Ep, z2p = [], []
+            for sgn in (1.0, -1.0):
+                hp = h.copy()
+                hp[j] += sgn * delta
+                v = _inverse_iteration(gpu, torch, b, hp, E, psi)
+                Ep.append(float(torch.dot(v, gpu.apply_H(b, hp, 0.0, v))))
+                z2p.append(abs(gpu.twist_expect(b, v)[0]) ** 2)
+            dE_fd = (Ep[0] - Ep[1]) / (2 * delta)
+            dz2_fd = (z2p[0] - z2p[1]) / (2 * delta)
+            eE, ez = abs(dE[j] - dE_fd), abs(dz2[j] - dz2_fd) / max(1.0, abs(dz2[j]))
+            say(f"  L={L} seed={seed} site={j + 1} gap>={gap:.1e} dE={dE[j]:+.9f} fd={dE_fd:+.9f} "
+                f"dz2={dz2[j]:+.6e} fd={dz2_fd:+.6e} minres={info.iters}")
+            worst_E, worst_z = max(worst_E, eE), max(worst_z, ez)
+    return worst_E, worst_z
+
+
+def test_eig_grad_fd_by_inverse_iteration_L18(gpu, torch):
+    """Derivatives of a mid-spectrum eigenpair at L=18 against finite
+    differences of eigenpairs obtained without the adjoint code. Step 1e-7:
+    the central-difference error is ~ delta^2 |V|^3 / gap^2 for E and
+    ~ delta^2 |V|^3 / gap^3 relative to d|z|^2/dh ~ |V| / gap for |z|^2,
+    both below the tolerances for gaps >= 1e-4; rounding of E' (~1e-13)
+    divided by 2 delta gives ~1e-6."""
+    say("eig_grad vs FD by inverse iteration, L=18")
+    eE, ez = _fd_subset(gpu, torch, 18, seeds=(0,), sites=(0, 7, 12))
+    assert eE <= 2e-5
+    assert ez <= 1e-3
+
+
+@pytest.mark.skipif(not __import__("os").environ.get("MBL_LONG_TESTS"),
+                    reason="L=20 subset (3 sites x 2 seeds) takes several minutes; set MBL_LONG_TESTS=1")
+def test_eig_grad_fd_by_inverse_iteration_L20(gpu, torch):
+    say("eig_grad vs FD by inverse iteration, L=20, 3 sites x 2 seeds")
+    eE, ez = _fd_subset(gpu, torch, 20, seeds=(0, 1), sites=(0, 9, 16))
+    assert eE <= 2e-5
+    assert ez <= 1e-3
