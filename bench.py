@@ -146,6 +146,21 @@ def eig_leg(mbl, torch, L, nev, R, batched_mixed=False):
         out["single_" + prec] = {"value": round(dt / max(res.nconv, 1), 4), "nconv": int(res.nconv),
                                  "realizations": 1, "seconds": round(dt, 3), "steps": int(res.steps),
                                  "minres_iters": int(res.minres_iters)}
+        if prec == "fp64":
+            # adjoint derivatives dE/dh and d|z|^2/dh of every converged pair
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            its = 0
+            for k in range(res.nconv):
+                _, _, _, ginfo = mbl.eig_grad(b, fields[0], res.evals[k],
+                                             res.evecs[:, k].contiguous(), tol=1e-12)
+                its += ginfo.iters
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            progress(f"eig leg L={L} adjoint: {dt / max(res.nconv, 1):.2f} s per pair")
+            out["adjoint_fp64"] = {"value": round(dt / max(res.nconv, 1), 4),
+                                   "unit": "s per eigenpair (all L derivatives of E and |z|^2)",
+                                   "minres_iters_per_pair": its // max(res.nconv, 1)}
         if prec != "fp64" and not batched_mixed:
             continue
         bb = mbl.Basis(L, tune.best_lo_bits(L, R, "fp64" if prec == "fp64" else "fp32"))
