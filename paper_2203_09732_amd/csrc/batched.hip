@@ -594,9 +594,11 @@ struct mbl_batch_s {
 
 namespace mbl {
 
-// Workgroups of the batched row kernels: one 1024-thread workgroup per
-// compute unit (measured: a second resident workgroup per CU slows the
-// gather-bound apply), fewer for small bases, whole XCD slices once large.
+// Workgroups of the batched row kernels: enough 16-wave workgroups for every
+// chunk to get its R / 2 waves (a chunk of 64 rows needs R / 2 wave-steps),
+// at most one 1024-thread workgroup per compute unit (measured: a second
+// resident workgroup per CU slows the gather-bound apply), whole XCD slices
+// once large.
 static int device_cus(int device) {
   static int cached[64] = {0};
   if (device < 0 || device >= 64) return 256;
@@ -612,10 +614,11 @@ static int device_cus(int device) {
   return cached[device];
 }
 
-static int bgrid(const mbl_basis_s* b) {
-  int g = (b->nchunks + (kBWG / 64) - 1) / (kBWG / 64);
-  g = std::max(1, std::min({g, kBGrid, device_cus(b->device)}));
-  return g >= 64 ? (g / 8) * 8 : g;
+static int bgrid(const mbl_basis_s* b, int R) {
+  const int64_t wave_steps = (int64_t)b->nchunks * std::max(1, R / 2);
+  int64_t g = (wave_steps + (kBWG / 64) - 1) / (kBWG / 64);
+  g = std::max<int64_t>(1, std::min<int64_t>({g, kBGrid, device_cus(b->device)}));
+  return g >= 64 ? (int)(g / 8) * 8 : (int)g;
 }
 
 static bool batched_split_supported(const mbl_basis_s* b) {
@@ -641,7 +644,7 @@ template <typename T, int MODE, bool GUARD>
 static mbl_status launch_bapply(const mbl_basis_s* b, const BatchDev& Q, const BState* S,
                                 const T* x, T* y, double* partials, hipStream_t s) {
   const size_t lds = blds_bytes(Q.R, b->L, b->nlo);
-  const dim3 g(bgrid(b)), blk(kBWG);
+  const dim3 g(bgrid(b, Q.R)), blk(kBWG);
   const DevBasis B = b->dev();
 #define MBL_CASE(LL, NN)                                                                    \
   case LL * 64 + NN:                                                                       \
@@ -658,7 +661,7 @@ static mbl_status launch_bresidual(const mbl_basis_s* b, const BatchDev& Q, int 
                                    const double* rhs, const double* x, double* res,
                                    double* partials, hipStream_t s) {
   const size_t lds = blds_bytes(Q.R, b->L, b->nlo);
-  const dim3 g(bgrid(b)), blk(kBWG);
+  const dim3 g(bgrid(b, Q.R)), blk(kBWG);
   const DevBasis B = b->dev();
 #define MBL_CASE(LL, NN)                                                                       \
   case LL * 64 + NN:                                                                          \
@@ -676,7 +679,7 @@ static mbl_status launch_binit(const mbl_basis_s* b, const BatchDev& Q, int kind
                                const double* src, const double* scale, T* z0, T* z1, T* q1, T* d0,
                                T* d1, T* x, double* partials, hipStream_t s) {
   const size_t lds = blds_bytes(Q.R, b->L, b->nlo);
-  const dim3 g(bgrid(b)), blk(kBWG);
+  const dim3 g(bgrid(b, Q.R)), blk(kBWG);
   const DevBasis B = b->dev();
 #define MBL_CASE(LL, NN)                                                                        \
   case LL * 64 + NN:                                                                           \
@@ -694,7 +697,7 @@ static mbl_status launch_bzq(const mbl_basis_s* b, const BatchDev& Q, int kind, 
                              const T* p, const T* zk, T* zkm1, T* qn, double* partials,
                              hipStream_t s) {
   const size_t lds = blds_bytes(Q.R, b->L, b->nlo);
-  const dim3 g(bgrid(b)), blk(kBWG);
+  const dim3 g(bgrid(b, Q.R)), blk(kBWG);
   const DevBasis B = b->dev();
 #define MBL_CASE(LL, NN)                                                                        \
   case LL * 64 + NN:                                                                           \
@@ -760,7 +763,7 @@ static mbl_status bminres_core(mbl_basis_s* b, mbl_batch_s* bw, const BatchDev& 
   for (int i = 0; i < kRing; ++i) qr.q[i] = Qv[i] = (T*)bw->q[i];
   T* D[2] = {(T*)bw->d[0], (T*)bw->d[1]};
   T* P = (T*)bw->p;
-  const int G = bgrid(b);
+  const int G = bgrid(b, R);
   BState* S = bw->S;
   // z_0 in Z[0], z_1 in Z[1], q_1 in Qv[1], d_0 in D[0], d_{-1} in D[1]
   MBL_TRY(launch_binit<T>(b, Q, precond, src, scale_dev, Z[0], Z[1], Qv[1], D[0], D[1], x,
@@ -909,7 +912,7 @@ static mbl_status bminres_run(mbl_basis_s* b, mbl_batch_s* bw, int precision, in
   std::vector<int> fp32_phase(R, 1);
   for (int cycle = 0;; ++cycle) {
     MBL_TRY(launch_bresidual(b, Q, precond, rhs, x, bw->r64, bw->partials1, s));
-    MBL_TRY(breduce_host(bw, bw->partials1, bgrid(b), 2, sums.data(), s));
+    MBL_TRY(breduce_host(bw, bw->partials1, bgrid(b, R), 2, sums.data(), s));
     bool any = false, any_fp64 = false;
     double worst = 0;
     for (int r = 0; r < R; ++r) {
@@ -943,7 +946,7 @@ static mbl_status bminres_run(mbl_basis_s* b, mbl_batch_s* bw, int precision, in
         std::vector<double> ones(R, 1.0);
         MBL_TRY(baxpby(bw, n, ones, bw->t64, ones, x, s));
         MBL_TRY(launch_bresidual(b, Q, precond, rhs, x, bw->r64, bw->partials1, s));
-        MBL_TRY(breduce_host(bw, bw->partials1, bgrid(b), 2, sums.data(), s));
+        MBL_TRY(breduce_host(bw, bw->partials1, bgrid(b, R), 2, sums.data(), s));
         for (int r = 0; r < R; ++r) phi[r] = std::sqrt(sums[2 * r]);
       }
       break;
@@ -1426,7 +1429,7 @@ mbl_status mbl_twist_expect_batched(mbl_basis b, mbl_batch w, const double* psi_
   MBL_ARG(nvec >= 1, "nvec must be >= 1");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int R = w->R, L = b->L;
-  const int G = bgrid(b);
+  const int G = bgrid(b, R);
   MBL_ARG((size_t)G * R * 2 <= w->part_elems, "internal: partials too small");
   BTwistTab T{};
   const double pi = 3.14159265358979323846;
