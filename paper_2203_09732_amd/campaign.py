@@ -11,8 +11,10 @@ interrupted campaign resumes where it stopped.
 """
 from __future__ import annotations
 
+import argparse
 import json
 import os
+import sys
 import time
 from dataclasses import dataclass
 
@@ -109,3 +111,43 @@ def run(tasks, nev: int, results_path: str | None = None, precision: str = "fp64
                 log(f"L={L} batch {start // R} R={R} ({real} real) {t_total:.1f}s "
                     f"steps={list(res.steps[:real])} nconv={list(res.nconv[:real])}")
     return records
+
+
+def main(argv=None):
+    """Run the mixed-size campaign of seeded realizations 0 .. count-1 (chain
+    length and disorder strength drawn per realization) and print one summary
+    line per chain length.
+
+        python -m paper_2203_09732_amd.campaign --count 512 --nev 6 --out results.jsonl
+    """
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    from workloads import batched_realizations
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--count", type=int, default=512)
+    ap.add_argument("--nev", type=int, default=6)
+    ap.add_argument("--out", default=None, help="JSON lines, one per realization (resumable)")
+    ap.add_argument("--max-R", type=int, default=MAX_R)
+    ap.add_argument("--precision", default="fp64")
+    a = ap.parse_args(argv)
+    tasks = [Task(r.index, r.L, r.h, r.fields) for r in batched_realizations(a.count)]
+    t0 = time.perf_counter()
+    recs = run(tasks, a.nev, results_path=a.out, precision=a.precision, max_R=a.max_R,
+               log=lambda m: print(m, flush=True))
+    wall = time.perf_counter() - t0
+    by_L = {}
+    for rec in recs:
+        d = by_L.setdefault(rec["L"], {"realizations": 0, "pairs": 0, "batches": set(), "seconds": 0.0})
+        d["realizations"] += 1
+        d["pairs"] += rec["nconv"]
+        if (rec["batch_R"], rec["batch_seconds"]) not in d["batches"]:
+            d["batches"].add((rec["batch_R"], rec["batch_seconds"]))
+            d["seconds"] += rec["batch_seconds"]
+    for L, d in sorted(by_L.items()):
+        print(json.dumps({"L": L, "realizations": d["realizations"], "converged_pairs": d["pairs"],
+                          "seconds": round(d["seconds"], 2),
+                          "s_per_pair": round(d["seconds"] / max(d["pairs"], 1), 4)}), flush=True)
+    print(json.dumps({"total_seconds": round(wall, 2), "realizations": len(recs)}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

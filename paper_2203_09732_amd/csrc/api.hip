@@ -128,8 +128,11 @@ static void free_ws(mbl_workspace_s* w) {
   hipFree(w->sync);
   if (w->h_state) hipHostFree(w->h_state);
   if (w->h_red) hipHostFree(w->h_red);
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 2; ++i) {
     if (w->ev[i]) hipEventDestroy(w->ev[i]);
+    if (w->graph[i]) hipGraphExecDestroy(w->graph[i]);
+  }
+  if (w->cap) hipStreamDestroy(w->cap);
   delete w;
 }
 

@@ -157,6 +157,12 @@ struct mbl_workspace_s {
   mbl::MinresState* h_state = nullptr;  // pinned host, 4 slots
   double* h_red = nullptr;              // pinned host, 256 doubles
   hipEvent_t ev[2] = {nullptr, nullptr};
+  // captured MINRES iterations per vector type (0: FP64, 1: FP32) and the
+  // kernel arguments they were captured with
+  hipGraphExec_t graph[2] = {nullptr, nullptr};
+  std::vector<unsigned char> graph_key[2];
+  hipStream_t cap = nullptr;            // capture stream
+  int graph_mode = -1;                  // -1: unset (environment), 0: eager, 1: graphs
 };
 
 namespace mbl {

@@ -23,6 +23,9 @@
 #include <cmath>
 #include <cstdlib>
 #include <string>
+#include <vector>
+#include <type_traits>
+#include <cstring>
 
 namespace mbl {
 
@@ -564,22 +567,84 @@ static mbl_status minres_core(mbl_basis_s* b, const FieldArgs& F, const double* 
     if (last.done) done = true;
     return MBL_OK;
   };
+  auto iteration = [&](int64_t k, hipStream_t st) -> mbl_status {
+    const MinresState* Sin = S + ((k - 1) & 1);
+    MinresState* Sout = S + (k & 1);
+    T* qk = Q[k & 1];
+    T* qn = Q[(k + 1) & 1];
+    T* zk = Z[k & 1];
+    T* zkm1 = Z[(k + 1) & 1];
+    T* dkm1 = D[(k - 1) & 1];
+    T* dkm2 = D[k & 1];
+    MBL_HIP(launch_minres_apply<T>(b, F, Sin, qk, P, ws->partials1, dfl, st));
+    hipLaunchKernelGGL((k_minres_zq<T>), dim3(G), dim3(kWG), lds, st, B, F, precond, Sin,
+                       ws->partials1, G, P, zk, zkm1, qn, ws->partials2, defl, ws->partials3);
+    hipLaunchKernelGGL((k_minres_dx<T>), dim3(FG), dim3(kWG), 0, st, n, Sin, Sout,
+                       ws->partials1, G, ws->partials2, G, tol, kmax, qk, dkm1, dkm2, x);
+    MBL_HIP(hipGetLastError());
+    return MBL_OK;
+  };
+  // The buffers of iteration k depend only on k & 1 and every kernel reads its
+  // scalars and done flag from device memory, so kGraphIters iterations are
+  // captured once (on the workspace's own stream) and replayed on the
+  // caller's stream; a replay after convergence is a sequence of no-op
+  // launches. The graph holds its kernel arguments (fields and shift, tol,
+  // kmax, x, the preconditioner, the deflation vector), so it is captured
+  // again when any of them changes.
+  constexpr int64_t kGraphIters = 16;
+  if (ws->graph_mode < 0) {
+    const char* e = getenv("MBL_MINRES_GRAPHS");
+    ws->graph_mode = (e && std::string(e) == "0") ? 0 : 1;
+  }
+  const bool use_graph = ws->graph_mode == 1 && kmax >= kChunkIters;
+  const int ti = std::is_same<T, float>::value ? 1 : 0;
+  if (use_graph) {
+    std::vector<unsigned char> key(sizeof(FieldArgs) + 2 * sizeof(double) + sizeof(int64_t) +
+                                   2 * sizeof(void*) + sizeof(int));
+    unsigned char* kp = key.data();
+    auto put = [&](const void* v, size_t sz) {
+      std::memcpy(kp, v, sz);
+      kp += sz;
+    };
+    put(&F, sizeof(FieldArgs));
+    put(&tol, sizeof(double));
+    put(&theta, sizeof(double));
+    put(&kmax, sizeof(int64_t));
+    const void* xp = x;
+    const void* dp = defl;
+    put(&xp, sizeof(void*));
+    put(&dp, sizeof(void*));
+    put(&precond, sizeof(int));
+    hipGraphExec_t& gx = ws->graph[ti];
+    if (gx && ws->graph_key[ti] != key) {
+      (void)hipGraphExecDestroy(gx);
+      gx = nullptr;
+    }
+    if (!gx) {
+      if (!ws->cap) MBL_HIP(hipStreamCreateWithFlags(&ws->cap, hipStreamNonBlocking));
+      hipGraph_t g = nullptr;
+      MBL_HIP(hipStreamBeginCapture(ws->cap, hipStreamCaptureModeThreadLocal));
+      mbl_status cst = MBL_OK;
+      for (int64_t k = 1; k <= kGraphIters && cst == MBL_OK; ++k) cst = iteration(k, ws->cap);
+      hipError_t ee = hipStreamEndCapture(ws->cap, &g);
+      if (cst != MBL_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return cst;
+      }
+      MBL_HIP(ee);
+      ee = hipGraphInstantiate(&gx, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      MBL_HIP(ee);
+      ws->graph_key[ti] = key;
+    }
+  }
   while (!done && issued < kmax) {
     const int64_t k_end = std::min(kmax, issued + kChunkIters);
-    for (int64_t k = issued + 1; k <= k_end; ++k) {
-      const MinresState* Sin = S + ((k - 1) & 1);
-      MinresState* Sout = S + (k & 1);
-      T* qk = Q[k & 1];
-      T* qn = Q[(k + 1) & 1];
-      T* zk = Z[k & 1];
-      T* zkm1 = Z[(k + 1) & 1];
-      T* dkm1 = D[(k - 1) & 1];
-      T* dkm2 = D[k & 1];
-      MBL_HIP(launch_minres_apply<T>(b, F, Sin, qk, P, ws->partials1, dfl, s));
-      hipLaunchKernelGGL((k_minres_zq<T>), dim3(G), dim3(kWG), lds, s, B, F, precond, Sin,
-                         ws->partials1, G, P, zk, zkm1, qn, ws->partials2, defl, ws->partials3);
-      hipLaunchKernelGGL((k_minres_dx<T>), dim3(FG), dim3(kWG), 0, s, n, Sin, Sout,
-                         ws->partials1, G, ws->partials2, G, tol, kmax, qk, dkm1, dkm2, x);
+    if (use_graph && k_end - issued == kChunkIters) {
+      for (int64_t rep = 0; rep < kChunkIters / kGraphIters; ++rep)
+        MBL_HIP(hipGraphLaunch(ws->graph[ti], s));
+    } else {
+      for (int64_t k = issued + 1; k <= k_end; ++k) MBL_TRY(iteration(k, s));
     }
     MBL_HIP(hipGetLastError());
     issued = k_end;

@@ -76,3 +76,38 @@ def test_batched_minres_graph_replays_match_eager(gpu, torch):
         xg, ig, pg, _ = gpu.minres_solve_batched(b, graph_bt, fields, sig, Bt, tol=1e-10)
         assert np.array_equal(ie, ig)
         assert torch.equal(xe, xg)
+
+
+def test_campaign_mixed_sizes_sample_vs_oracle(gpu, torch):
+    """Realizations of the mixed-size workload (chain length and disorder
+    strength drawn per realization, seeded) with L in {14, 16}: sigma equals
+    the oracle's midpoint, the nev = 6 eigenvalues nearest it equal the
+    oracle's (dense at L = 14, sparse shift-invert at L = 16), and each z is
+    within the bound 2 ||delta psi|| <= 2 resid / gap of the oracle's."""
+    from paper_2203_09732_amd import campaign
+    from workloads import batched_realizations
+    reals = [r for r in batched_realizations(40) if r.L in (14, 16)][:10]
+    assert {r.L for r in reals} == {14, 16}
+    tasks = [campaign.Task(r.index, r.L, r.h, r.fields) for r in reals]
+    say(f"campaign sample of the mixed-size workload: {[(r.index, r.L, r.h) for r in reals]}")
+    recs = campaign.run(tasks, nev=6, log=say)
+    assert len(recs) == len(reals)
+    for rec in recs:
+        r = next(x for x in reals if x.index == rec["index"])
+        H = model.hamiltonian_csr(r.L, r.fields)
+        lo, hi = lanczos.extremal_eigenvalues(H)
+        assert abs(rec["sigma"] - 0.5 * (lo + hi)) <= 1e-9 * max(abs(lo), abs(hi))
+        if r.L == 14:
+            E, V = lanczos.eigenpairs_dense(H.toarray(), rec["sigma"], 6)
+            w = np.linalg.eigvalsh(H.toarray())
+        else:
+            E, V = lanczos.eigenpairs_shift_invert_sparse(H, rec["sigma"], 10)
+            keep = np.sort(np.argsort(np.abs(E - rec["sigma"]))[:6])
+            w, E, V = E, E[keep], V[:, keep]
+        assert rec["nconv"] == 6
+        assert np.all(np.abs(np.array(rec["evals"]) - E) / np.maximum(np.abs(E), 1) <= 1e-10)
+        gaps = np.array([np.min(np.abs(np.delete(w, np.argmin(np.abs(w - e))) - e)) for e in E])
+        z = np.array(rec["z_re"]) + 1j * np.array(rec["z_im"])
+        zr = twist.twist_overlap(r.L, V)
+        bound = 2 * np.array(rec["resid"]) / gaps + 1e-9
+        assert np.all(np.abs(z - zr) <= bound), (np.abs(z - zr), bound)
