@@ -292,7 +292,8 @@ def l22_projection(minres):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this benchmark measures one GPU (realizations are independent, "
+                                   "so more GPUs would each run their own batches); use --gpus 1"}))
         sys.exit(2)
     import torch
 

@@ -93,7 +93,10 @@ mbl_status mbl_basis_rank(mbl_basis b, const uint32_t* states_dev, int64_t count
 /* ---- workspace -------------------------------------------------------------
  * Device scratch for MINRES (its recurrence vectors) and for up to mmax
  * Lanczos basis vectors, 0 <= mmax <= 1000 (MBL_ERR_ARG otherwise).
- * precision selects the MINRES vector type. */
+ * precision selects the MINRES vector type. Size: 8 n (12 + mmax + 1) bytes
+ * for mmax > 0 (8 n 12 for mmax = 0) plus about 1 MB: the MINRES vectors
+ * z, q, d (two each) and p, an FP32-inner correction, a residual and a
+ * scratch vector, the Lanczos w and x, and the Lanczos basis. */
 mbl_status mbl_workspace_create(mbl_basis b, int mmax, int precision, mbl_workspace* ws);
 void mbl_workspace_free(mbl_workspace ws);
 /* Device bytes held by the workspace. */
@@ -116,13 +119,18 @@ mbl_status mbl_precond_apply(mbl_basis b, const double* h_host, double sigma, in
 /* ---- preconditioned MINRES for (H - sigma I) x = b (App. A, Alg. 2) --------
  * rhs_dev: n doubles. x_dev: n doubles, initial guess on entry (x0), solution
  * on exit. Stops when |phi_k| < tol (phi_k = ||b - A x_k||_{M^{-1}}) or after
- * kmax iterations (MBL_WARN_NOCONV). With MBL_FP32_INNER the inner solves run
- * in FP32 and restart from the FP64 residual until its M^{-1}-norm is < tol.
- * Synchronizes stream. info may be NULL. */
+ * kmax iterations (MBL_WARN_NOCONV). With MBL_FP32_INNER the solve runs in
+ * cycles: an FP32 MINRES solve of A e = r / ||r|| to a relative 1e-3 (smaller
+ * near the end), x += ||r|| e in FP64, r = b - A x recomputed in FP64. A cycle
+ * that fails to cut ||r||_{M^{-1}} tenfold (FP32 rounding limits a cycle to
+ * about u_32 times the condition number), or the 60th cycle, ends the FP32
+ * phase and FP64 MINRES finishes on the current residual. The stop test is
+ * then the FP64 ||r||_{M^{-1}} < tol. Synchronizes stream. info may be NULL. */
 typedef struct {
   int64_t iters;       /* MINRES iterations, summed over restarts */
-  int32_t restarts;    /* FP64 residual restarts (0 in MBL_FP64) */
-  double phi;          /* final |phi| (recurrence estimate) */
+  int32_t restarts;    /* FP32 cycles (0 in MBL_FP64) */
+  double phi;          /* final |phi|: the recurrence estimate (MBL_FP64), the
+                          recomputed FP64 ||r||_{M^{-1}} (MBL_FP32_INNER) */
   double true_res;     /* ||b - (H - sigma) x||_2 recomputed in FP64 */
 } mbl_minres_info;
 mbl_status mbl_minres_solve(mbl_basis b, const double* h_host, double sigma,
@@ -177,9 +185,12 @@ mbl_status mbl_eig_residual(mbl_basis b, const double* h_host, const double* E_h
                             const double* psi_dev, int64_t ld, int nvec,
                             double* resid_host, void* stream);
 
-/* ---- sigma = (E_min + E_max) / 2 (Sec. IV A) by Lanczos on H with full
- * reorthogonalisation; E_min, E_max converge to rel_tol * max(|E|).
- * mmax bounds the steps (0 = default 300). Synchronizes stream. */
+/* ---- sigma = (E_min + E_max) / 2 (Sec. IV A) by Lanczos on H without
+ * reorthogonalisation (the extremal Ritz values converge first and are not
+ * affected by the copies loss of orthogonality creates), from a seeded start
+ * vector; stops when the residual estimates of both extremes are below
+ * rel_tol * max(|E_min|, |E_max|). mmax bounds the steps (0 = default 300;
+ * MBL_WARN_NOCONV if reached). Synchronizes stream. */
 mbl_status mbl_sigma_midpoint(mbl_basis b, const double* h_host, double rel_tol, int mmax,
                               double* emin, double* emax, double* sigma, void* stream);
 
@@ -191,8 +202,10 @@ mbl_status mbl_sigma_midpoint(mbl_basis b, const double* h_host, double rel_tol,
  *    adjoint solve (H - E) lambda = P g with g_a = 4 c_a Re(conj(z) u_a),
  *    P = I - psi psi^T, lambda re-projected orthogonal to psi, then
  *    d|z|^2/dh_j = sum_a lambda_a c_a s_j(a). The solve is preconditioned
- *    MINRES (Alg. 2) with sigma = E, tolerance tol and kmax iterations; it
- *    needs a workspace with MINRES vectors (any mmax).
+ *    MINRES (Alg. 2) on (H - E + psi psi^T / ||psi||^2) lambda = P g: the
+ *    rank-one term lifts the near-null direction psi of H - E and leaves the
+ *    solution for a right-hand side orthogonal to psi unchanged. Tolerance
+ *    tol, kmax iterations; any workspace of the basis (any mmax).
  * z_host[2] (Re, Im of z) and info may be NULL. MBL_WARN_NOCONV if the solve
  * missed tol. Synchronizes stream. */
 mbl_status mbl_eig_grad(mbl_basis b, const double* h_host, double E, const double* psi_dev,
@@ -211,9 +224,11 @@ mbl_status mbl_eig_grad(mbl_basis b, const double* h_host, double E, const doubl
  * with 32-bit byte offsets); otherwise MBL_ERR_ARG. L must be one of
  * 12, 14, ..., 32 and the basis's lo_bits one of the splits the library has
  * batched kernels for (the default split of every such L, and the
- * alternatives the autotuner measures). The batch workspace holds the recurrence vectors
- * of all realizations and up to mmax Lanczos blocks (n * R * (mmax + 1)
- * doubles). */
+ * alternatives the autotuner measures). The batch workspace holds the
+ * recurrence vectors of all realizations (z, d and p, a ring of 8 q vectors
+ * for the d/x update grouped over 4 iterations, the FP32-inner correction,
+ * residual, scratch, Lanczos w and x: 18 n R doubles) and up to mmax + 1
+ * Lanczos blocks of n R doubles. */
 typedef struct mbl_batch_s* mbl_batch;
 mbl_status mbl_batch_create(mbl_basis b, int R, int mmax, int nevmax, mbl_batch* out);
 void mbl_batch_free(mbl_batch w);
