@@ -1,0 +1,72 @@
+"""Host-side logic that needs no GPU: batch-width choice and resume of the
+campaign driver, the autotuner's cache keys, and the bench's projection of
+the per-eigenpair cost."""
+import json
+
+import pytest
+
+
+@pytest.fixture(scope="module")
+def pkg():
+    import paper_2203_09732_amd as m
+    return m
+
+
+def test_widest_batch_is_a_power_of_two_within_limits(pkg):
+    from paper_2203_09732_amd import campaign
+    for L in (12, 14, 16, 18, 20, 22, 24, 26):
+        for want in (1, 2, 3, 5, 8, 17, 32, 100):
+            R = campaign.widest_batch(L, want)
+            assert R & (R - 1) == 0 and 2 <= R <= campaign.MAX_R
+            assert R <= max(2, want)
+            # the per-realization field tables of R realizations fit the budget
+            assert R == 2 or R * 16 * ((L + 3) // 4) * 8 <= 30 * 1024
+
+
+def test_campaign_resume_reads_done_indices(pkg, tmp_path):
+    from paper_2203_09732_amd import campaign
+    p = tmp_path / "r.jsonl"
+    assert campaign._done_indices(str(p)) == set()
+    with open(p, "w") as fh:
+        fh.write(json.dumps({"index": 3}) + "\n")
+        fh.write("not json\n")
+        fh.write(json.dumps({"index": 7, "L": 14}) + "\n")
+    assert campaign._done_indices(str(p)) == {3, 7}
+
+
+def test_tuner_cache_key_and_default(pkg, monkeypatch, tmp_path):
+    from paper_2203_09732_amd import tune
+    assert tune._key(22, 32, "fp64") == "L22_R32_fp64"
+    cache = tmp_path / "tuning.json"
+    cache.write_text(json.dumps({"gfx950": {"L22_R32_fp64": {"lo_bits": 11}}}))
+    monkeypatch.setattr(tune, "CACHE", str(cache))
+    monkeypatch.setattr(tune, "_arch", lambda: "gfx950")
+    assert tune.best_lo_bits(22, 32, "fp64") == 11
+    assert tune.best_lo_bits(22, 16, "fp64") == 0       # unknown: library default
+    monkeypatch.setattr(tune, "_arch", lambda: "gfx942")
+    assert tune.best_lo_bits(22, 32, "fp64") == 0       # other architecture
+
+
+def test_bench_projection_arithmetic():
+    import bench
+    minres = {k: {"us_per_realization_iter": 10.0} for k in
+              ("single_fp64", "single_fp32_inner", "batched_fp64", "batched_fp32_inner")}
+    out = bench.l22_projection(minres)
+    expect = 10e-6 * bench.L22_ITERS["fp64"] * bench.L22_STEPS_20 / 20
+    assert abs(out["single_fp64"] - round(expect, 1)) < 1e-9
+    assert out["pairs"] == 20 and out["steps"] == bench.L22_STEPS_20
+
+
+def test_bench_refuses_more_than_one_gpu(capsys):
+    import sys
+
+    import bench
+    argv = sys.argv
+    sys.argv = ["bench.py", "--gpus", "2"]
+    try:
+        with pytest.raises(SystemExit) as e:
+            bench.main()
+    finally:
+        sys.argv = argv
+    assert e.value.code == 2
+    assert "one GPU" in capsys.readouterr().out
