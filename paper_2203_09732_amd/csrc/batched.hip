@@ -26,10 +26,13 @@
 namespace mbl {
 
 // ---------------------------------------------------------------------------
-// y = (H_r - sigma_r) x_r for every realization. MODE 1: partial sums of
-// x.y per realization; GUARD: skip realizations whose state is done.
+// y = (H_r - sigma_r) x_r for every realization. MODE 1 is the product of
+// MINRES iteration k: it first takes the Givens step of iteration k - 1 for
+// every realization (gv; the same in every workgroup, stored by workgroup
+// 0), skips realizations whose state is then done (GUARD), and writes
+// partial sums of x.y per realization.
 template <typename T, int MODE, bool GUARD, int L, int NLO>
-__global__ __launch_bounds__(kBWG) void k_bapply(DevBasis B, BatchDev Q, const BState* S,
+__global__ __launch_bounds__(kBWG) void k_bapply(DevBasis B, BatchDev Q, BGivens gv,
                                                  const T* __restrict__ x, T* __restrict__ y,
                                                  double* __restrict__ partials) {
   using T2 = typename Pair<T>::type;
@@ -42,7 +45,21 @@ __global__ __launch_bounds__(kBWG) void k_bapply(DevBasis B, BatchDev Q, const B
   const __amdgpu_buffer_rsrc_t rx = brsrc(x, bytes), ry = brsrc(y, bytes);
   const int lane_p = (threadIdx.x & 63) % (R >> 1);
   bool live = true;
-  if (GUARD) live = !(S[2 * lane_p].done && S[2 * lane_p + 1].done);
+  if (GUARD) {
+    if (gv.active) {
+      const double qz = bsum_partials(gv.part2, gv.G, R, t.red);
+      if (threadIdx.x < R) {
+        const int r = threadIdx.x;
+        const BState so = bgivens_step(gv.Sprev[r], gv.alpha[r], qz, gv.tol, gv.kmax);
+        if (blockIdx.x == 0) gv.Scur[r] = so;
+        t.shared_r[r] = so.done ? 1.0 : 0.0;
+      }
+    } else if (threadIdx.x < R) {
+      t.shared_r[threadIdx.x] = gv.Scur[threadIdx.x].done ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    live = !(t.shared_r[2 * lane_p] != 0.0 && t.shared_r[2 * lane_p + 1] != 0.0);
+  }
   double acc0 = 0.0, acc1 = 0.0;
   if (live) {
     bfor_rows(B, t, R, [&](uint32_t, uint32_t hi, uint32_t lo, uint32_t j, uint32_t block0,
@@ -171,6 +188,8 @@ __global__ __launch_bounds__(kBWG) void k_binit(DevBasis B, BatchDev Q, int kind
 template <typename T, int L>
 __global__ __launch_bounds__(kBWG) void k_bzq(DevBasis B, BatchDev Q, int kind,
                                               const BState* __restrict__ S,
+                                              const double* __restrict__ part1, int G,
+                                              double* __restrict__ alpha_out,
                                               const T* __restrict__ p, const T* __restrict__ zk,
                                               T* __restrict__ zkm1, T* __restrict__ qn,
                                               double* __restrict__ partials) {
@@ -179,15 +198,27 @@ __global__ __launch_bounds__(kBWG) void k_bzq(DevBasis B, BatchDev Q, int kind,
   extern __shared__ __align__(16) unsigned char smem[];
   const BTables t = bsetup(B, Q, smem);
   __syncthreads();
+  // alpha_k = q_k . p_k / beta_k^2 from the product's partials (the same in
+  // every workgroup; workgroup 0 keeps it for the Givens step)
+  const double qp = bsum_partials(part1, G, R, t.red);
+  if (threadIdx.x < R) {
+    const int r = threadIdx.x;
+    const double beta = S[r].beta;
+    const double alpha = qp / (beta * beta);
+    t.shared_r[r] = alpha;
+    if (blockIdx.x == 0) alpha_out[r] = alpha;
+  }
+  __syncthreads();
   const uint32_t rs = (uint32_t)t.rsh + (sizeof(T) == 8 ? 3u : 2u);
   const uint32_t bytes = (uint32_t)B.n << rs;
   const __amdgpu_buffer_rsrc_t rp = brsrc(p, bytes), rz = brsrc(zk, bytes),
                                rzo = brsrc(zkm1, bytes), rq = brsrc(qn, bytes);
   const int lp = (threadIdx.x & 63) % PR;
   const BState s0 = S[2 * lp], s1 = S[2 * lp + 1];
+  const double al0 = t.shared_r[2 * lp], al1 = t.shared_r[2 * lp + 1];
   const bool live0 = !s0.done, live1 = !s1.done;
-  const double c10 = 1.0 / s0.beta, c20 = s0.alpha / s0.beta, c30 = s0.beta / s0.beta_prev;
-  const double c11 = 1.0 / s1.beta, c21 = s1.alpha / s1.beta, c31 = s1.beta / s1.beta_prev;
+  const double c10 = 1.0 / s0.beta, c20 = al0 / s0.beta, c30 = s0.beta / s0.beta_prev;
+  const double c11 = 1.0 / s1.beta, c21 = al1 / s1.beta, c31 = s1.beta / s1.beta_prev;
   double a0 = 0, a1 = 0;
   if (live0 || live1) {
     bfor_rows(B, t, R, [&](uint32_t, uint32_t, uint32_t, uint32_t j, uint32_t block0, uint32_t a,
@@ -245,62 +276,14 @@ __global__ void k_binit_state(const double* __restrict__ partials, int G, int R,
   }
 }
 
-// One workgroup per realization: alpha_k from the apply partials.
-__global__ void k_balpha(const double* __restrict__ partials, int G, int R, BState* S) {
-  __shared__ double red[kWavesPerWG];
-  const int r = blockIdx.x;
-  if (S[r].done) return;
-  double v = 0;
-  for (int g = threadIdx.x; g < G; g += blockDim.x) v += partials[(size_t)g * R + r];
-  const double qp = block_sum_all(v, red);
-  if (threadIdx.x == 0) S[r].alpha = qp / (S[r].beta * S[r].beta);
-}
-
-// One workgroup per realization: beta_{k+1}, Givens rotation, d/x
-// coefficients, next state into Sout (carried unchanged once done).
-__global__ void k_bgivens(const double* __restrict__ partials, int G, int R, double tol,
-                          int64_t kmax, const BState* __restrict__ Sin, BState* __restrict__ Sout) {
-  __shared__ double red[kWavesPerWG];
-  const int r = blockIdx.x;
-  const BState si = Sin[r];
-  if (si.done) {
-    if (threadIdx.x == 0) {
-      BState so = si;
-      so.d_tau = 0.0;
-      Sout[r] = so;
-    }
-    return;
-  }
-  double v = 0;
-  for (int g = threadIdx.x; g < G; g += blockDim.x) v += partials[(size_t)g * R + r];
-  const double qz = block_sum_all(v, red);
-  if (threadIdx.x == 0) {
-    const double alpha = si.alpha, beta = si.beta;
-    const double beta_next = sqrt(qz);
-    const double delta = si.c * si.dhat + si.s * alpha;
-    const double gamma_hat = -si.s * si.dhat + si.c * alpha;
-    const double eps_next = si.s * beta_next;
-    const double dhat_next = si.c * beta_next;
-    const double gamma = sqrt(gamma_hat * gamma_hat + beta_next * beta_next);
-    const double c = gamma_hat / gamma, s = beta_next / gamma;
-    const double tau = c * si.phi, phi = -s * si.phi;
-    BState so = si;
-    so.d_inv_beta = 1.0 / beta;
-    so.d_delta = delta;
-    so.d_eps = si.eps;
-    so.d_inv_gamma = 1.0 / gamma;
-    so.d_tau = tau;
-    so.beta_prev = beta;
-    so.beta = beta_next;
-    so.c = c;
-    so.s = s;
-    so.dhat = dhat_next;
-    so.eps = eps_next;
-    so.phi = phi;
-    so.k = si.k + 1;
-    so.bad = !isfinite(phi) || !isfinite(alpha) || !isfinite(beta_next);
-    so.done = so.bad || !(fabs(phi) >= tol && so.k < kmax);
-    Sout[r] = so;
+// The Givens step of the last issued iteration (one workgroup of kBWG
+// threads; the same arithmetic as the product's prologue).
+__global__ __launch_bounds__(kBWG) void k_bgivens_last(BGivens gv, int R) {
+  __shared__ double red[kLdsRed * kBMaxR];
+  const double qz = bsum_partials(gv.part2, gv.G, R, red);
+  if (threadIdx.x < R) {
+    const int r = threadIdx.x;
+    gv.Scur[r] = bgivens_step(gv.Sprev[r], gv.alpha[r], qz, gv.tol, gv.kmax);
   }
 }
 
@@ -577,6 +560,7 @@ struct mbl_batch_s {
   double* red = nullptr;     // R * 64
   double* scale = nullptr;   // R
   double* scale2 = nullptr;  // R
+  double* alph = nullptr;    // 2 * R: MINRES alpha_k by the parity of k
   mbl::BState* h_state = nullptr;   // pinned, 4 * R
   double* h_red = nullptr;          // pinned, R * 64
   double* h_stage = nullptr;        // pinned, R * (L + 1) + 4 R
@@ -641,14 +625,14 @@ static bool batched_split_supported(const mbl_basis_s* b) {
   }
 
 template <typename T, int MODE, bool GUARD>
-static mbl_status launch_bapply(const mbl_basis_s* b, const BatchDev& Q, const BState* S,
+static mbl_status launch_bapply(const mbl_basis_s* b, const BatchDev& Q, const BGivens& gv,
                                 const T* x, T* y, double* partials, hipStream_t s) {
   const size_t lds = blds_bytes(Q.R, b->L, b->nlo);
   const dim3 g(bgrid(b, Q.R)), blk(kBWG);
   const DevBasis B = b->dev();
 #define MBL_CASE(LL, NN)                                                                    \
   case LL * 64 + NN:                                                                       \
-    hipLaunchKernelGGL((k_bapply<T, MODE, GUARD, LL, NN>), g, blk, lds, s, B, Q, S, x, y,  \
+    hipLaunchKernelGGL((k_bapply<T, MODE, GUARD, LL, NN>), g, blk, lds, s, B, Q, gv, x, y, \
                        partials);                                                          \
     break;
   MBL_BDISPATCH(MBL_CASE)
@@ -694,15 +678,15 @@ static mbl_status launch_binit(const mbl_basis_s* b, const BatchDev& Q, int kind
 
 template <typename T>
 static mbl_status launch_bzq(const mbl_basis_s* b, const BatchDev& Q, int kind, const BState* S,
-                             const T* p, const T* zk, T* zkm1, T* qn, double* partials,
-                             hipStream_t s) {
+                             const double* part1, double* alpha_out, const T* p, const T* zk,
+                             T* zkm1, T* qn, double* partials, hipStream_t s) {
   const size_t lds = blds_bytes(Q.R, b->L, b->nlo);
   const dim3 g(bgrid(b, Q.R)), blk(kBWG);
   const DevBasis B = b->dev();
 #define MBL_CASE(LL, NN)                                                                        \
   case LL * 64 + NN:                                                                           \
-    hipLaunchKernelGGL((k_bzq<T, LL>), g, blk, lds, s, B, Q, kind, S, p, zk, zkm1, qn,        \
-                       partials);                                                              \
+    hipLaunchKernelGGL((k_bzq<T, LL>), g, blk, lds, s, B, Q, kind, S, part1, (int)g.x,      \
+                       alpha_out, p, zk, zkm1, qn, partials);                                  \
     break;
   MBL_BDISPATCH(MBL_CASE)
 #undef MBL_CASE
@@ -778,26 +762,49 @@ static mbl_status bminres_core(mbl_basis_s* b, mbl_batch_s* bw, const BatchDev& 
     MBL_HIP(hipGetLastError());
     return MBL_OK;
   };
-  // one iteration k of Alg. 2 for all realizations; the d/x update follows
-  // every kDxGroup iterations
+  // The Givens step of iteration k - 1 (state k - 1 in slot (k - 1) % kRing,
+  // alpha_{k-1} in alph[(k - 1) & 1]).
+  auto givens_args = [&](int64_t k) {
+    BGivens gv;
+    gv.part2 = bw->partials2;
+    gv.alpha = bw->alph + ((k - 1) & 1) * R;
+    gv.Sprev = S + ((k + kRing - 2) % kRing) * R;
+    gv.Scur = S + ((k - 1) % kRing) * R;
+    gv.G = G;
+    gv.active = k >= 2;
+    gv.tol = tol;
+    gv.kmax = kmax;
+    return gv;
+  };
+  // Iteration k of Alg. 2 for all realizations, two row launches: the
+  // product p = A q_k, which first takes the Givens step of iteration k - 1
+  // (and skips realizations that are then done), and the z/q update, which
+  // first forms alpha_k. The d/x update of iterations k - 4 .. k - 1 runs
+  // between them once their Givens steps are known.
   auto iteration = [&](int64_t k, hipStream_t st) -> mbl_status {
-    BState* Sin = S + ((k - 1) % kRing) * R;
-    BState* Sout = S + (k % kRing) * R;
-    MBL_TRY((launch_bapply<T, 1, true>(b, Q, Sin, Qv[k % kRing], P, bw->partials1, st)));
-    hipLaunchKernelGGL(k_balpha, dim3(R), dim3(kWG), 0, st, bw->partials1, G, R, Sin);
-    MBL_TRY(launch_bzq<T>(b, Q, precond, Sin, P, Z[k & 1], Z[(k + 1) & 1], Qv[(k + 1) % kRing],
-                          bw->partials2, st));
-    hipLaunchKernelGGL(k_bgivens, dim3(R), dim3(kWG), 0, st, bw->partials2, G, R, tol, kmax, Sin,
-                       Sout);
-    MBL_HIP(hipGetLastError());
-    if (k % kDxGroup == 0) MBL_TRY(dx_group(k - kDxGroup + 1, kDxGroup, st));
+    const BGivens gv = givens_args(k);
+    MBL_TRY((launch_bapply<T, 1, true>(b, Q, gv, Qv[k % kRing], P, bw->partials1, st)));
+    if (k > kDxGroup && (k - 1) % kDxGroup == 0) MBL_TRY(dx_group(k - kDxGroup, kDxGroup, st));
+    MBL_TRY(launch_bzq<T>(b, Q, precond, gv.Scur, bw->partials1, bw->alph + (k & 1) * R, P,
+                          Z[k & 1], Z[(k + 1) & 1], Qv[(k + 1) % kRing], bw->partials2, st));
     return MBL_OK;
   };
-  // The buffers of iteration k depend only on k mod kRing, and every kernel reads
-  // its scalars (and the done flags) from device memory, so a block of
-  // kGraphIters iterations is captured once per workspace and replayed; a
-  // replay after convergence is a sequence of no-op launches. tol and kmax
-  // are kernel arguments, so the graph is rebuilt when they change.
+  // After the last issued iteration K: its Givens step, then the d/x update
+  // of the iterations not yet covered (those after the last full group).
+  auto finish = [&](int64_t K, hipStream_t st) -> mbl_status {
+    BGivens gv = givens_args(K + 1);
+    hipLaunchKernelGGL(k_bgivens_last, dim3(1), dim3(kBWG), 0, st, gv, R);
+    MBL_HIP(hipGetLastError());
+    const int64_t covered = K >= 1 ? kDxGroup * ((K - 1) / kDxGroup) : 0;
+    if (K > covered) MBL_TRY(dx_group(covered + 1, (int)(K - covered), st));
+    return MBL_OK;
+  };
+  // Iteration 1 runs eagerly; then blocks of kGraphIters iterations (2..17,
+  // 18..33, ...), which use buffers and state slots that depend only on k mod
+  // kRing and read their scalars and done flags from device memory, are
+  // captured once per workspace and replayed (a replay after convergence is
+  // a sequence of no-op launches). tol and kmax are kernel arguments, so the
+  // graph is captured again when they change.
   constexpr int64_t kGraphIters = 16;
   const int ti = std::is_same<T, float>::value ? 1 : 0;
   if (bw->graph_mode < 0) {
@@ -817,7 +824,7 @@ static mbl_status bminres_core(mbl_basis_s* b, mbl_batch_s* bw, const BatchDev& 
     hipGraph_t g = nullptr;
     MBL_HIP(hipStreamBeginCapture(bw->cap, hipStreamCaptureModeThreadLocal));
     mbl_status cst = MBL_OK;
-    for (int64_t k = 1; k <= kGraphIters && cst == MBL_OK; ++k) cst = iteration(k, bw->cap);
+    for (int64_t k = 2; k <= kGraphIters + 1 && cst == MBL_OK; ++k) cst = iteration(k, bw->cap);
     hipError_t ee = hipStreamEndCapture(bw->cap, &g);
     if (cst != MBL_OK) {
       if (g) (void)hipGraphDestroy(g);
@@ -831,7 +838,7 @@ static mbl_status bminres_core(mbl_basis_s* b, mbl_batch_s* bw, const BatchDev& 
     bw->graph_kmax[ti][precond] = kmax;
     bw->graph_x[ti][precond] = (void*)x;
   }
-  const int64_t kChunkIters = 32;   // a multiple of kGraphIters
+  const int64_t kChunkIters = 2 * kGraphIters;
   int64_t issued = 0;
   int pending = 0, slot = 0;
   bool done = false;
@@ -840,9 +847,12 @@ static mbl_status bminres_core(mbl_basis_s* b, mbl_batch_s* bw, const BatchDev& 
     bool all = true;
     for (int r = 0; r < R; ++r) all = all && bw->h_state[which * R + r].done;
     if (all) done = true;
-    fin.assign(bw->h_state + which * R, bw->h_state + which * R + R);
     return MBL_OK;
   };
+  if (kmax >= 1) {
+    MBL_TRY(iteration(1, s));
+    issued = 1;
+  }
   while (!done && issued < kmax) {
     const int64_t k_end = std::min(kmax, issued + kChunkIters);
     if (use_graph && k_end - issued == kChunkIters) {
@@ -852,10 +862,9 @@ static mbl_status bminres_core(mbl_basis_s* b, mbl_batch_s* bw, const BatchDev& 
       for (int64_t k = issued + 1; k <= k_end; ++k) MBL_TRY(iteration(k, s));
     }
     issued = k_end;
-    if (issued % kDxGroup != 0)   // only at kmax: the d/x update of the last iterations
-      MBL_TRY(dx_group(issued - issued % kDxGroup + 1, (int)(issued % kDxGroup), s));
-    MBL_HIP(hipMemcpyAsync(bw->h_state + slot * R, S + (issued % kRing) * R, sizeof(BState) * R,
-                           hipMemcpyDeviceToHost, s));
+    // the state after iteration issued - 1 is the newest one on the device
+    MBL_HIP(hipMemcpyAsync(bw->h_state + slot * R, S + ((issued - 1) % kRing) * R,
+                           sizeof(BState) * R, hipMemcpyDeviceToHost, s));
     MBL_HIP(hipEventRecord(bw->ev[slot], s));
     ++pending;
     if (pending == 2) {
@@ -865,6 +874,11 @@ static mbl_status bminres_core(mbl_basis_s* b, mbl_batch_s* bw, const BatchDev& 
     slot ^= 1;
   }
   if (pending > 0) MBL_TRY(check(slot ^ 1));
+  if (issued >= 1) MBL_TRY(finish(issued, s));
+  MBL_HIP(hipMemcpyAsync(bw->h_state, S + (issued % kRing) * R, sizeof(BState) * R,
+                         hipMemcpyDeviceToHost, s));
+  MBL_HIP(hipStreamSynchronize(s));
+  fin.assign(bw->h_state, bw->h_state + R);
   for (const BState& st : fin)
     if (st.bad) {
       set_error("batched MINRES met a non-finite value");
@@ -1013,7 +1027,7 @@ double gershgorin_bound(const mbl_basis_s* b, const double* h);
 static mbl_status bapply_norms(mbl_basis_s* b, mbl_batch_s* bw, const double* v, double* out,
                                hipStream_t s) {
   BatchDev Q{bw->h, bw->c0, bw->R};
-  MBL_TRY((launch_bapply<double, 0, false>(b, Q, nullptr, v, bw->t64, nullptr, s)));
+  MBL_TRY((launch_bapply<double, 0, false>(b, Q, BGivens{}, v, bw->t64, nullptr, s)));
   MBL_TRY(bdot_host(bw, b->n, bw->t64, bw->t64, out, s));
   for (int r = 0; r < bw->R; ++r) out[r] = std::sqrt(out[r]);
   return MBL_OK;
@@ -1212,7 +1226,7 @@ static void free_batch(mbl_batch_s* w) {
   if (!w) return;
   double* bufs[] = {w->h, w->c0, w->z[0], w->z[1], w->d[0], w->d[1], w->p,
                     w->e, w->r64, w->t64, w->w, w->x, w->V, w->coef, w->ycoef, w->partials1,
-                    w->partials2, w->red, w->scale, w->scale2};
+                    w->partials2, w->red, w->scale, w->scale2, w->alph};
   for (double* p : bufs) (void)hipFree(p);
   for (double* p : w->q) (void)hipFree(p);
   (void)hipFree(w->S);
@@ -1273,6 +1287,7 @@ static mbl_status create_batch(mbl_basis_s* b, int R, int mmax, int nevmax, mbl_
   A(&w->red, (size_t)std::max(R * 64, (mmax + 1) * R));
   A(&w->scale, R);
   A(&w->scale2, R);
+  A(&w->alph, 2 * (size_t)R);
   if (st == MBL_OK && hipMalloc((void**)&w->S, sizeof(BState) * kRing * R) != hipSuccess) {
     (void)hipGetLastError();
     set_error("device allocation failed (batched state)");
@@ -1348,7 +1363,7 @@ mbl_status mbl_apply_H_batched(mbl_basis b, mbl_batch w, const double* h_host,
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   MBL_TRY(bupload(w, h_host, sigma_host, s));
   BatchDev Q{w->h, w->c0, w->R};
-  return launch_bapply<double, 0, false>(b, Q, nullptr, x_dev, y_dev, nullptr, s);
+  return launch_bapply<double, 0, false>(b, Q, BGivens{}, x_dev, y_dev, nullptr, s);
 }
 
 mbl_status mbl_apply_H_batched_f32(mbl_basis b, mbl_batch w, const double* h_host,
@@ -1364,7 +1379,7 @@ mbl_status mbl_apply_H_batched_f32(mbl_basis b, mbl_batch w, const double* h_hos
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   MBL_TRY(bupload(w, h_host, sigma_host, s));
   BatchDev Q{w->h, w->c0, w->R};
-  return launch_bapply<float, 0, false>(b, Q, nullptr, x_dev, y_dev, nullptr, s);
+  return launch_bapply<float, 0, false>(b, Q, BGivens{}, x_dev, y_dev, nullptr, s);
 }
 
 mbl_status mbl_minres_solve_batched(mbl_basis b, mbl_batch w, const double* h_host,

@@ -34,10 +34,12 @@ struct BatchDev {
 // addressed by (lo << 1) ^ (mask << 1) alone; lo_state (2^nlo uint16); the
 // field table lut[(k * 16 + v) * R + r] = sum of h_r over the set bits of
 // nibble value v at nibble position k, so a lane reads its realization pair
-// with one 16-byte access; c0[R]; reduction scratch.
+// with one 16-byte access; c0[R]; reduction scratch; per-realization values
+// shared by the workgroup (done flags, MINRES alpha).
 __host__ __device__ constexpr size_t blds_bytes(int R, int L, int nlo) {
   return ((size_t)4 << nlo) + (size_t)R * (((L + 3) >> 2) * 16) * sizeof(double) +
-         (size_t)R * sizeof(double) + kLdsRed * kBMaxR * sizeof(double);
+         (size_t)R * sizeof(double) + kLdsRed * kBMaxR * sizeof(double) +
+         kBMaxR * sizeof(double);
 }
 
 struct BTables {
@@ -46,6 +48,7 @@ struct BTables {
   const double* lut;          // [nnib][16][R]
   const double* c0;           // [R]
   double* red;                // [waves][R]
+  double* shared_r;           // [kBMaxR] per-realization values for the workgroup
   int rsh;                    // log2 R
 };
 
@@ -76,7 +79,7 @@ __device__ __forceinline__ BTables bsetup(const DevBasis& B, const BatchDev& Q, 
     ss[t] = gs[t];
   }
   return BTables{reinterpret_cast<const unsigned char*>(rank), state, lut, c0, red,
-                 31 - __builtin_clz((unsigned)R)};
+                 red + kLdsRed * kBMaxR, 31 - __builtin_clz((unsigned)R)};
 }
 
 // a_aa - sigma_r for the lane's realization pair (2p, 2p + 1); the field sum
@@ -291,5 +294,86 @@ __device__ __forceinline__ double bblock_sum(double acc0, double acc1, double* r
   }
   return s;
 }
+
+
+// Per-realization sums of the G workgroup partials partials[g * R + r], the
+// same in every workgroup that calls it: thread t adds g = t / R, t / R +
+// nt / R, ... of realization r = t % R; lanes of one realization inside a
+// wave are combined by a butterfly, then the waves in index order. Thread
+// r < R returns the sum for realization r, the others 0. red: [waves][R].
+__device__ __forceinline__ double bsum_partials(const double* __restrict__ partials, int G, int R,
+                                                double* red) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int r = t % R, per = nt / R;
+  double v = 0.0;
+  for (int g = t / R; g < G; g += per) v += partials[(size_t)g * R + r];
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1)
+    if (o >= R) v += __shfl_xor(v, o, 64);
+  const int lane = t & 63, wave = t >> 6;
+  __syncthreads();
+  if (lane < R) red[wave * R + lane] = v;
+  __syncthreads();
+  double sum = 0.0;
+  if (t < R) {
+    const int nw = nt >> 6;
+    for (int w = 0; w < nw; ++w) sum += red[w * R + t];
+  }
+  __syncthreads();
+  return sum;
+}
+
+// One step of the MINRES scalar recurrence of Alg. 2 for one realization:
+// from the state after iteration k - 1, alpha_k and q_{k+1} . z_{k+1}, the
+// state after iteration k (beta_{k+1}, the Givens rotation, the d/x
+// coefficients of iteration k, phi_k, done). A done state is carried with a
+// zero step.
+__device__ __forceinline__ BState bgivens_step(const BState& si, double alpha, double qz,
+                                               double tol, int64_t kmax) {
+  BState so = si;
+  if (si.done) {
+    so.d_tau = 0.0;
+    return so;
+  }
+  const double beta = si.beta;
+  const double beta_next = sqrt(qz);
+  const double delta = si.c * si.dhat + si.s * alpha;
+  const double gamma_hat = -si.s * si.dhat + si.c * alpha;
+  const double eps_next = si.s * beta_next;
+  const double dhat_next = si.c * beta_next;
+  const double gamma = sqrt(gamma_hat * gamma_hat + beta_next * beta_next);
+  const double c = gamma_hat / gamma, s = beta_next / gamma;
+  const double tau = c * si.phi, phi = -s * si.phi;
+  so.alpha = alpha;
+  so.d_inv_beta = 1.0 / beta;
+  so.d_delta = delta;
+  so.d_eps = si.eps;
+  so.d_inv_gamma = 1.0 / gamma;
+  so.d_tau = tau;
+  so.beta_prev = beta;
+  so.beta = beta_next;
+  so.c = c;
+  so.s = s;
+  so.dhat = dhat_next;
+  so.eps = eps_next;
+  so.phi = phi;
+  so.k = si.k + 1;
+  so.bad = !isfinite(phi) || !isfinite(alpha) || !isfinite(beta_next);
+  so.done = so.bad || !(fabs(phi) >= tol && so.k < kmax);
+  return so;
+}
+
+// Arguments of the Givens step of iteration k - 1 that the MINRES product of
+// iteration k computes first (every workgroup the same; workgroup 0 stores it).
+struct BGivens {
+  const double* part2;   // q_k . z_k partials of the previous z/q update
+  const double* alpha;   // alpha_{k-1} per realization
+  const BState* Sprev;   // state after iteration k - 2
+  BState* Scur;          // receives the state after iteration k - 1
+  int G;
+  int active;            // 0 at k = 1: Scur already holds the initial state
+  double tol;
+  int64_t kmax;
+};
 
 }  // namespace mbl
