@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <new>
@@ -1150,6 +1151,12 @@ static mbl_status bsi_lanczos_run(mbl_basis_s* b, mbl_batch_s* bw, const double*
       }
       if (conv || broke) active[r] = 0;
       else all_conv = false;
+    }
+    if (std::getenv("MBL_VERBOSE")) {   // one line per lockstep Lanczos step (long runs)
+      int live = 0;
+      for (int r = 0; r < R; ++r) live += active[r];
+      std::fprintf(stderr, "[mbl] batched si_lanczos step %d: %d of %d realizations still "
+                   "stepping, minres total %lld\n", k, live, R, (long long)total_iters);
     }
     if (all_conv) break;
   }

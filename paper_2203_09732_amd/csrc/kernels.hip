@@ -235,12 +235,8 @@ __global__ __launch_bounds__(kWG) void k_splitmix(int64_t n, uint64_t seed, doub
 // host launch wrappers
 
 int row_grid(const mbl_basis_s* b) {
-  static const int cap = [] {
-    const char* e = getenv("MBL_ROW_GRID_MAX");
-    return e ? std::max(8, std::min(kMaxPartials, atoi(e))) : kMaxPartials;
-  }();
   int g = (b->nchunks + kWavesPerWG - 1) / kWavesPerWG;
-  if (g > cap) g = cap;
+  if (g > kMaxPartials) g = kMaxPartials;
   if (g < 1) g = 1;
   return g >= 64 ? (g / 8) * 8 : g;   // whole XCD slices once the grid is large
 }

@@ -10,6 +10,8 @@
 #include "mbl_internal.h"
 
 #include <algorithm>
+#include <cstdlib>
+#include <cstdio>
 #include <chrono>
 #include <cmath>
 #include <mutex>
@@ -264,6 +266,8 @@ mbl_status si_lanczos_run(mbl_basis_s* b, const double* h, double sigma, int nev
   std::vector<double> theta, Y;
   std::vector<int> sel;
   int64_t total_iters = 0;
+  // MBL_VERBOSE=1: one line per Lanczos step on stderr (long runs)
+  const bool verbose = std::getenv("MBL_VERBOSE") != nullptr;
   bool breakdown = false, converged = false, minres_warn = false;
   int k = 0;
   double beta_k = 0.0;   // beta_k multiplying v_{k-1}; v_0 = 0
@@ -329,6 +333,10 @@ mbl_status si_lanczos_run(mbl_basis_s* b, const double* h, double sigma, int nev
         if (!ok) converged = false;
       }
     }
+    if (verbose)
+      std::fprintf(stderr, "[mbl] si_lanczos step %d: minres %lld iterations (total %lld), %s\n", k,
+                   (long long)mi.iters, (long long)total_iters,
+                   converged ? "converged" : (breakdown ? "breakdown" : "continuing"));
     if (converged || breakdown) break;
     beta_k = beta_next;
   }

@@ -405,12 +405,8 @@ __global__ __launch_bounds__(kWG) void k_add_scaled_f32(int64_t n, double scale,
 
 
 static int flat_grid(int64_t n) {
-  static const int cap = [] {
-    const char* e = getenv("MBL_FLAT_GRID_MAX");
-    return e ? std::max(8, atoi(e)) : 2048;
-  }();
   int64_t g = (n + kWG - 1) / kWG;
-  if (g > cap) g = cap;
+  if (g > 2048) g = 2048;
   return (int)(g < 1 ? 1 : g);
 }
 
