@@ -206,7 +206,7 @@ def largest_leg(mbl, torch, steps=20):
     free1 = torch.cuda.mem_get_info()[0]
     out["workspace_mmax70_bytes"] = ws.bytes
     out["device_bytes_taken"] = int(free0 - free1)
-    out["linear_model_bytes_8n(12+71)"] = 8 * n * (12 + 71)
+    out["linear_model_bytes_8n(13+71)"] = 8 * n * (13 + 71)
     out["paper_model_bytes_8n(9+m)_m70"] = 8 * n * (9 + 70)
     t = time.perf_counter()
     lo, hi, sigma = mbl.sigma_midpoint(b, h, 1e-10)

@@ -93,9 +93,9 @@ mbl_status mbl_basis_rank(mbl_basis b, const uint32_t* states_dev, int64_t count
 /* ---- workspace -------------------------------------------------------------
  * Device scratch for MINRES (its recurrence vectors) and for up to mmax
  * Lanczos basis vectors, 0 <= mmax <= 1000 (MBL_ERR_ARG otherwise).
- * precision selects the MINRES vector type. Size: 8 n (12 + mmax + 1) bytes
- * for mmax > 0 (8 n 12 for mmax = 0) plus about 1 MB: the MINRES vectors
- * z, q, d (two each) and p, an FP32-inner correction, a residual and a
+ * precision selects the MINRES vector type. Size: 8 n (13 + mmax + 1) bytes
+ * for mmax > 0 (8 n 13 for mmax = 0) plus about 1 MB: the MINRES vectors
+ * z and d (two each), q (three) and p, an FP32-inner correction, a residual and a
  * scratch vector, the Lanczos w and x, and the Lanczos basis. */
 mbl_status mbl_workspace_create(mbl_basis b, int mmax, int precision, mbl_workspace* ws);
 void mbl_workspace_free(mbl_workspace ws);

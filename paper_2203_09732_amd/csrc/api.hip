@@ -108,9 +108,10 @@ static void free_ws(mbl_workspace_s* w) {
   if (!w) return;
   for (int i = 0; i < 2; ++i) {
     hipFree(w->z[i]);
-    hipFree(w->q[i]);
     hipFree(w->d[i]);
   }
+  for (int i = 0; i < 3; ++i) hipFree(w->q[i]);
+  hipFree(w->alpha);
   hipFree(w->p);
   hipFree(w->e);
   hipFree(w->r64);
@@ -157,9 +158,9 @@ static mbl_status create_ws(mbl_basis_s* b, int mmax, int precision, bool minres
   if (minres_vectors) {
     for (int i = 0; i < 2; ++i) {
       A((double**)&w->z[i], n);
-      A((double**)&w->q[i], n);
       A((double**)&w->d[i], n);
     }
+    for (int i = 0; i < 3; ++i) A((double**)&w->q[i], n);
     A((double**)&w->p, n);
     A((double**)&w->e, n);
   }
@@ -175,6 +176,7 @@ static mbl_status create_ws(mbl_basis_s* b, int mmax, int precision, bool minres
   A(&w->partials3, (size_t)kMaxPartials);
   A(&w->red_out, 256);
   A(&w->state, 2);
+  A(&w->alpha, 2);
   A(&w->sync, kSyncWords);
   if (st == MBL_OK) {
     if (hipHostMalloc((void**)&w->h_state, 4 * sizeof(MinresState)) != hipSuccess ||

@@ -28,16 +28,29 @@ namespace mbl {
 
 // ---------------------------------------------------------------------------
 // y = (H - sigma) x. MODE 0: plain; 1: partial sums of x.y; 2: partial sums of
-// y.y. GUARD: return at once when the MINRES state S is done. (L, NLO) = (0, 0)
-// is the runtime-split form.
+// y.y. GUARD: the product of MINRES iteration k, which first takes the Givens
+// step of iteration k - 1 (G; every workgroup the same, workgroup 0 stores
+// it) and returns at once when the state is then done. (L, NLO) = (0, 0) is
+// the runtime-split form.
 template <typename T, int MODE, bool GUARD, int L, int NLO>
-__global__ __launch_bounds__(kWG) void k_apply(DevBasis B, FieldArgs F, const MinresState* S,
+__global__ __launch_bounds__(kWG) void k_apply(DevBasis B, FieldArgs F, MinresGivens G,
                                                const T* __restrict__ x, T* __restrict__ y,
                                                double* __restrict__ partials, Defl D) {
-  if (GUARD && S->done) return;
   extern __shared__ __align__(16) unsigned char smem[];
   const RowTables t = setup_tables<L>(B, F, smem);
   __syncthreads();
+  if (GUARD) {
+    bool done;
+    if (G.active) {
+      const double qz = reduce_partials(G.part2, G.P2, t.red);
+      const MinresState so = minres_givens_step(*G.Sprev, *G.alpha, qz, G.tol, G.kmax);
+      if (blockIdx.x == 0 && threadIdx.x == 0) *G.Scur = so;
+      done = so.done != 0;
+    } else {
+      done = G.Scur->done != 0;
+    }
+    if (done) return;
+  }
   // rank-one term theta v (v . x) of a deflated MINRES operator
   double dcoef = 0.0;
   if (GUARD && D.v) dcoef = D.theta * reduce_partials(D.c_part, D.P, t.red);
@@ -250,7 +263,7 @@ static int dense_grid(int64_t n) {
 
 // launch the (L, NLO) instance matching the basis, else the runtime form
 template <typename T, int MODE, bool GUARD>
-static hipError_t apply_dispatch(const mbl_basis_s* b, const FieldArgs& F, const MinresState* S,
+static hipError_t apply_dispatch(const mbl_basis_s* b, const FieldArgs& F, const MinresGivens& S,
                                  const T* x, T* y, double* partials, hipStream_t s,
                                  const Defl& D = Defl{}) {
   const dim3 g(row_grid(b)), blk(kWG);
@@ -275,9 +288,9 @@ template <typename T>
 hipError_t launch_apply(const mbl_basis_s* b, const FieldArgs& F, const T* x, T* y, int mode,
                         double* partials, int* nparts, hipStream_t s) {
   if (nparts) *nparts = row_grid(b);
-  if (mode == 0) return apply_dispatch<T, 0, false>(b, F, nullptr, x, y, partials, s);
-  if (mode == 1) return apply_dispatch<T, 1, false>(b, F, nullptr, x, y, partials, s);
-  return apply_dispatch<T, 2, false>(b, F, nullptr, x, y, partials, s);
+  if (mode == 0) return apply_dispatch<T, 0, false>(b, F, MinresGivens{}, x, y, partials, s);
+  if (mode == 1) return apply_dispatch<T, 1, false>(b, F, MinresGivens{}, x, y, partials, s);
+  return apply_dispatch<T, 2, false>(b, F, MinresGivens{}, x, y, partials, s);
 }
 template hipError_t launch_apply<double>(const mbl_basis_s*, const FieldArgs&, const double*,
                                          double*, int, double*, int*, hipStream_t);
@@ -285,15 +298,15 @@ template hipError_t launch_apply<float>(const mbl_basis_s*, const FieldArgs&, co
                                         int, double*, int*, hipStream_t);
 
 template <typename T>
-hipError_t launch_minres_apply(const mbl_basis_s* b, const FieldArgs& F, const MinresState* S,
+hipError_t launch_minres_apply(const mbl_basis_s* b, const FieldArgs& F, const MinresGivens& G,
                                const T* q, T* p, double* partials, const Defl& D, hipStream_t s) {
-  return apply_dispatch<T, 1, true>(b, F, S, q, p, partials, s, D);
+  return apply_dispatch<T, 1, true>(b, F, G, q, p, partials, s, D);
 }
 template hipError_t launch_minres_apply<double>(const mbl_basis_s*, const FieldArgs&,
-                                                const MinresState*, const double*, double*,
+                                                const MinresGivens&, const double*, double*,
                                                 double*, const Defl&, hipStream_t);
 template hipError_t launch_minres_apply<float>(const mbl_basis_s*, const FieldArgs&,
-                                               const MinresState*, const float*, float*, double*,
+                                               const MinresGivens&, const float*, float*, double*,
                                                const Defl&, hipStream_t);
 
 hipError_t launch_precond(const mbl_basis_s* b, const FieldArgs& F, int kind, const double* z,

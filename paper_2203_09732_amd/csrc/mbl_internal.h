@@ -107,6 +107,22 @@ struct MinresState {
   int64_t k;
   int32_t done;
   int32_t bad;     // non-finite value met
+  // coefficients of the d/x update of iteration k: d_k = (q_k d_inv_beta -
+  // d_delta d_{k-1} - d_eps d_{k-2}) d_inv_gamma, x_k = x_{k-1} + d_tau d_k
+  double d_inv_beta, d_delta, d_eps, d_inv_gamma, d_tau;
+};
+
+// The Givens step of iteration k - 1 that the MINRES product of iteration k
+// takes first (the same in every workgroup; workgroup 0 stores it).
+struct MinresGivens {
+  const double* part2 = nullptr;   // q_k . z_k partials of the previous z/q update
+  int P2 = 0;
+  const double* alpha = nullptr;   // alpha_{k-1}
+  const MinresState* Sprev = nullptr;   // state after iteration k - 2
+  MinresState* Scur = nullptr;          // receives the state after iteration k - 1
+  double tol = 0.0;
+  int64_t kmax = 0;
+  int active = 0;                  // 0 at k = 1: Scur holds the initial state
 };
 
 }  // namespace mbl
@@ -135,7 +151,7 @@ struct mbl_workspace_s {
   int64_t bytes = 0;
   // MINRES vectors: FP64 set or FP32 set (+ FP64 residual for restarts)
   void* z[2] = {nullptr, nullptr};
-  void* q[2] = {nullptr, nullptr};
+  void* q[3] = {nullptr, nullptr, nullptr};   // ring: q_{k-1}, q_k, q_{k+1}
   void* d[2] = {nullptr, nullptr};
   void* p = nullptr;
   void* e = nullptr;         // FP32 correction (FP32 inner form)
@@ -153,6 +169,7 @@ struct mbl_workspace_s {
   double* partials3 = nullptr;   // kMaxPartials
   double* red_out = nullptr;     // 256 doubles
   mbl::MinresState* state = nullptr;  // 2 slots
+  double* alpha = nullptr;            // 2 slots: MINRES alpha_k by the parity of k
   unsigned int* sync = nullptr;       // kSyncWords: grid barrier words (GridSync)
   mbl::MinresState* h_state = nullptr;  // pinned host, 4 slots
   double* h_red = nullptr;              // pinned host, 256 doubles
@@ -180,7 +197,7 @@ template <typename T>
 hipError_t launch_apply(const mbl_basis_s* b, const FieldArgs& F, const T* x, T* y, int mode,
                         double* partials, int* nparts, hipStream_t s);
 template <typename T>
-hipError_t launch_minres_apply(const mbl_basis_s* b, const FieldArgs& F, const MinresState* S,
+hipError_t launch_minres_apply(const mbl_basis_s* b, const FieldArgs& F, const MinresGivens& G,
                                const T* q, T* p, double* partials, const Defl& D, hipStream_t s);
 hipError_t launch_precond(const mbl_basis_s* b, const FieldArgs& F, int kind, const double* z,
                           double* q, hipStream_t s);

@@ -1,22 +1,23 @@
 // Preconditioned MINRES for (H - sigma I) x = b (App. A, Alg. 2) on gfx950.
 //
-// One iteration k is three launches on the same stream:
-//   1. p = A q_k with fused partial sums of q_k . p            (row kernel)
-//   2. alpha_k = q.p / beta_k^2; z_{k+1} = p/beta_k - (alpha_k/beta_k) z_k
+// Iteration k is two row launches on the same stream:
+//   1. the product p = A q_k with partial sums of q_k . p; it first takes the
+//      Givens step of iteration k - 1 (beta_k from the partials of q_k . z_k,
+//      the rotation, phi_{k-1}, the d/x coefficients of iteration k - 1) and
+//      returns at once when the solve is done (kernels.hip, k_apply GUARD);
+//   2. alpha_k = q_k . p / beta_k^2; z_{k+1} = p/beta_k - (alpha_k/beta_k) z_k
 //      - (beta_k/beta_{k-1}) z_{k-1}; q_{k+1} = M^{-1} z_{k+1} with M
-//      regenerated from the state bits; partial sums of q_{k+1} . z_{k+1}
-//                                                              (row kernel)
-//   3. beta_{k+1}, the Givens rotation, d_k and x_k += tau_k d_k
-//                                                              (flat kernel)
+//      regenerated from the state bits; partial sums of q_{k+1} . z_{k+1}; and
+//      the d/x update of iteration k - 1, d_{k-1} and x_{k-1} += tau d_{k-1}.
 // Every workgroup reduces the partial sums itself in the same fixed order,
 // so all workgroups hold bitwise identical scalars without a host round
-// trip. The scalar state lives in device memory in two slots (k & 1); once
-// |phi_k| < tol or k = kmax the state is marked done and later launches
-// return at once (the host checks the state one chunk of iterations behind).
+// trip. The scalar states live in device memory in two slots (k & 1); the
+// host checks them one chunk of iterations behind, and after the last
+// iteration one small launch takes its Givens step and d/x update.
 //
 // Vector slots: z_{k-1}/z_{k+1} share a buffer (updated in place), so do
-// d_{k-2}/d_k; q_k and q_{k+1} alternate. With p and x that is 8 n-vectors
-// besides b.
+// d_{k-3}/d_{k-1}; q_{k-1}, q_k, q_{k+1} use a ring of three. With p and x
+// that is 9 n-vectors besides b.
 #include "rows.h"
 
 #include <algorithm>
@@ -88,98 +89,90 @@ __global__ void k_minres_init_state(const double* __restrict__ partials, int P, 
   }
 }
 
-// ---- step 1: p = A q_k, partial sums of q_k . p: the apply kernel of
-// kernels.hip guarded by the done flag (launch_minres_apply).
-
-// ---- step 2: z_{k+1}, q_{k+1}, partial sums of q_{k+1} . z_{k+1} -------------
+// ---- step 2: alpha_k; z_{k+1}, q_{k+1}, partial sums of q_{k+1} . z_{k+1};
+// the d/x update of iteration k - 1 --------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(kWG) void k_minres_zq(DevBasis B, FieldArgs F, int kind,
-                                                   const MinresState* __restrict__ Sin,
-                                                   const double* __restrict__ part1, int P1,
-                                                   const T* __restrict__ p, const T* __restrict__ zk,
-                                                   T* __restrict__ zkm1, T* __restrict__ qnext,
-                                                   double* __restrict__ part2,
-                                                   const double* __restrict__ dv,
-                                                   double* __restrict__ part3) {
-  if (Sin->done) return;
+__global__ __launch_bounds__(kWG) void k_minres_zqdx(
+    DevBasis B, FieldArgs F, int kind, const MinresState* __restrict__ Sprev,
+    const MinresState* __restrict__ Scur, const double* __restrict__ part1, int P1,
+    double* __restrict__ alpha_out, const T* __restrict__ p, const T* __restrict__ zk,
+    T* __restrict__ zkm1, T* __restrict__ qnext, double* __restrict__ part2,
+    const double* __restrict__ dv, double* __restrict__ part3, const T* __restrict__ qprev,
+    T* __restrict__ dprev, const T* __restrict__ dprev2, T* __restrict__ x) {
+  const bool zq = !Scur->done;                 // iteration k is taken
+  const bool dx = Sprev && !Sprev->done;       // iteration k - 1 was taken
+  if (!zq && !dx) return;
   extern __shared__ __align__(16) unsigned char smem[];
   const RowTables t = setup_tables(B, F, smem);
-  const double qp = reduce_partials(part1, P1, t.red);
-  const double beta = Sin->beta, beta_prev = Sin->beta_prev;
-  const double alpha = qp / (beta * beta);
-  const double c1 = 1.0 / beta, c2 = alpha / beta, c3 = beta / beta_prev;
+  const MinresState sc = *Scur;
+  double alpha = 0.0;
+  if (zq) {
+    const double qp = reduce_partials(part1, P1, t.red);
+    alpha = qp / (sc.beta * sc.beta);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *alpha_out = alpha;
+  } else {
+    __syncthreads();
+  }
+  const double c1 = 1.0 / sc.beta, c2 = alpha / sc.beta, c3 = sc.beta / sc.beta_prev;
+  // d_{k-1} = (q_{k-1} / beta_{k-1} - delta d_{k-2} - eps d_{k-3}) / gamma, from
+  // the Givens step of iteration k - 1 (the state sc)
+  const double ib = sc.d_inv_beta, de = sc.d_delta, ep = sc.d_eps, ig = sc.d_inv_gamma,
+               tau = sc.d_tau;
   double acc = 0.0, acc3 = 0.0;
   for_rows(B, t, [&](uint32_t row, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t a) {
-    const double zn = c1 * (double)p[row] - c2 * (double)zk[row] - c3 * (double)zkm1[row];
-    const T zt = (T)zn;
-    int na;
-    const double dsh = row_diag<0>(B, F, t, a, na);
-    const T qt = (T)((double)zt / precond_value(kind, dsh, na));
-    zkm1[row] = zt;
-    qnext[row] = qt;
-    acc += (double)qt * (double)zt;
-    if (dv) acc3 += dv[row] * (double)qt;
+    if (dx) {
+      const double d = ((double)qprev[row] * ib - de * (double)dprev2[row] -
+                        ep * (double)dprev[row]) * ig;
+      const T dt = (T)d;
+      dprev[row] = dt;
+      x[row] = (T)((double)x[row] + tau * (double)dt);
+    }
+    if (zq) {
+      const double zn = c1 * (double)p[row] - c2 * (double)zk[row] - c3 * (double)zkm1[row];
+      const T zt = (T)zn;
+      int na;
+      const double dsh = row_diag<0>(B, F, t, a, na);
+      const T qt = (T)((double)zt / precond_value(kind, dsh, na));
+      zkm1[row] = zt;
+      qnext[row] = qt;
+      acc += (double)qt * (double)zt;
+      if (dv) acc3 += dv[row] * (double)qt;
+    }
   });
-  const double s = block_sum_all(acc, t.red);
-  if (threadIdx.x == 0) part2[blockIdx.x] = s;
-  if (dv) {
-    const double s3 = block_sum_all(acc3, t.red);
-    if (threadIdx.x == 0) part3[blockIdx.x] = s3;
+  if (zq) {
+    const double s = block_sum_all(acc, t.red);
+    if (threadIdx.x == 0) part2[blockIdx.x] = s;
+    if (dv) {
+      const double s3 = block_sum_all(acc3, t.red);
+      if (threadIdx.x == 0) part3[blockIdx.x] = s3;
+    }
   }
 }
 
-// ---- step 3: Givens rotation, d_k, x_k (flat kernel) -----------------------
-template <typename T>
-__global__ __launch_bounds__(kWG) void k_minres_dx(int64_t n, const MinresState* __restrict__ Sin,
-                                                   MinresState* __restrict__ Sout,
-                                                   const double* __restrict__ part1, int P1,
-                                                   const double* __restrict__ part2, int P2,
-                                                   double tol, int64_t kmax,
-                                                   const T* __restrict__ qk, const T* __restrict__ dkm1,
-                                                   T* __restrict__ dkm2, T* __restrict__ x) {
+// ---- after the last issued iteration K: its Givens step (one workgroup) ----
+__global__ __launch_bounds__(kWG) void k_minres_givens_last(MinresGivens G) {
   __shared__ double red[kWavesPerWG];
-  const MinresState si = *Sin;
-  if (si.done) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) *Sout = si;   // carry the final state forward
-    return;
-  }
-  const double qp = reduce_partials(part1, P1, red);
-  const double qz = reduce_partials(part2, P2, red);
-  const double beta = si.beta;
-  const double alpha = qp / (beta * beta);
-  const double beta_next = sqrt(qz);
-  const double delta = si.c * si.dhat + si.s * alpha;
-  const double gamma_hat = -si.s * si.dhat + si.c * alpha;
-  const double eps_next = si.s * beta_next;
-  const double dhat_next = si.c * beta_next;
-  const double gamma = sqrt(gamma_hat * gamma_hat + beta_next * beta_next);
-  const double c = gamma_hat / gamma;
-  const double s = beta_next / gamma;
-  const double tau = c * si.phi;
-  const double phi = -s * si.phi;
-  const double inv_beta = 1.0 / beta, inv_gamma = 1.0 / gamma;
-  const double eps = si.eps;
+  const double qz = reduce_partials(G.part2, G.P2, red);
+  if (threadIdx.x == 0) *G.Scur = minres_givens_step(*G.Sprev, *G.alpha, qz, G.tol, G.kmax);
+}
+
+// ---- and its d/x update: d_K, x_K (flat kernel) ------------------------------
+template <typename T>
+__global__ __launch_bounds__(kWG) void k_minres_dx_last(int64_t n, const MinresState* __restrict__ Sprev,
+                                                        const MinresState* __restrict__ Scur,
+                                                        const T* __restrict__ qk,
+                                                        T* __restrict__ dk,
+                                                        const T* __restrict__ dkm1,
+                                                        T* __restrict__ x) {
+  if (Sprev->done) return;
+  const MinresState sc = *Scur;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x) {
-    const double d = ((double)qk[i] * inv_beta - delta * (double)dkm1[i] - eps * (double)dkm2[i]) *
-                     inv_gamma;
+    const double d = ((double)qk[i] * sc.d_inv_beta - sc.d_delta * (double)dkm1[i] -
+                      sc.d_eps * (double)dk[i]) * sc.d_inv_gamma;
     const T dt = (T)d;
-    dkm2[i] = dt;
-    x[i] = (T)((double)x[i] + tau * (double)dt);
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    MinresState so;
-    so.beta_prev = beta;
-    so.beta = beta_next;
-    so.c = c;
-    so.s = s;
-    so.dhat = dhat_next;
-    so.eps = eps_next;
-    so.phi = phi;
-    so.k = si.k + 1;
-    so.bad = !isfinite(phi) || !isfinite(alpha) || !isfinite(beta_next);
-    so.done = so.bad || !(fabs(phi) >= tol && so.k < kmax);
-    *Sout = so;
+    dk[i] = dt;
+    x[i] = (T)((double)x[i] + sc.d_tau * (double)dt);
   }
 }
 
@@ -486,8 +479,8 @@ static mbl_status persistent_solve(mbl_basis_s* b, const FieldArgs& F, int preco
 // GPU whose L2 caches are private to each XCD, a barrier that makes one
 // workgroup's vector writes visible to the others needs device-scope release
 // and acquire fences, which write back and invalidate L2; measured, the
-// launch per iteration is faster from L = 16 up (13.9 against 17.2 us per
-// iteration at L = 16, 16 against 35 at L = 18) and the cooperative launch
+// launches per iteration are faster from L = 16 up (11.8 against 17.2 us
+// per iteration at L = 16, 14.7 against 35 at L = 18) and the cooperative launch
 // wins only on the smallest grids. MBL_MINRES_LAUNCH=iter|persistent forces
 // a form.
 constexpr int kPersistentMaxGrid = 32;
@@ -553,50 +546,61 @@ static mbl_status minres_core(mbl_basis_s* b, const FieldArgs& F, const double* 
     clear_error();
   }
 
-  const int64_t kChunkIters = 64;
-  int64_t issued = 0;
-  int pending = 0;       // status copies in flight (0..2)
-  int slot = 0;
-  bool done = false;
-  MinresState last{};
+  T* Qr[3] = {(T*)ws->q[0], (T*)ws->q[1], (T*)ws->q[2]};   // q_k in Qr[k % 3]
   const int FG = flat_grid(n);
-  // a state copy for the chunk ending at iteration k goes to h_state[slot]
-  auto check = [&](int which) -> mbl_status {
-    MBL_HIP(hipEventSynchronize(ws->ev[which]));
-    last = ws->h_state[which];
-    if (last.done) done = true;
-    return MBL_OK;
+  MinresGivens gbase;
+  gbase.part2 = ws->partials2;
+  gbase.P2 = G;
+  gbase.tol = tol;
+  gbase.kmax = kmax;
+  // the Givens step of iteration k - 1: state k - 1 into slot (k - 1) & 1,
+  // alpha_{k-1} in ws->alpha[(k - 1) & 1]
+  auto givens_args = [&](int64_t k) {
+    MinresGivens g = gbase;
+    g.alpha = ws->alpha + ((k - 1) & 1);
+    g.Sprev = S + (k & 1);
+    g.Scur = S + ((k - 1) & 1);
+    g.active = k >= 2;
+    return g;
   };
+  // iteration k: the product (after the Givens step of k - 1), then the z/q
+  // update of k with the d/x update of k - 1
   auto iteration = [&](int64_t k, hipStream_t st) -> mbl_status {
-    const MinresState* Sin = S + ((k - 1) & 1);
-    MinresState* Sout = S + (k & 1);
-    T* qk = Q[k & 1];
-    T* qn = Q[(k + 1) & 1];
-    T* zk = Z[k & 1];
-    T* zkm1 = Z[(k + 1) & 1];
-    T* dkm1 = D[(k - 1) & 1];
-    T* dkm2 = D[k & 1];
-    MBL_HIP(launch_minres_apply<T>(b, F, Sin, qk, P, ws->partials1, dfl, st));
-    hipLaunchKernelGGL((k_minres_zq<T>), dim3(G), dim3(kWG), lds, st, B, F, precond, Sin,
-                       ws->partials1, G, P, zk, zkm1, qn, ws->partials2, defl, ws->partials3);
-    hipLaunchKernelGGL((k_minres_dx<T>), dim3(FG), dim3(kWG), 0, st, n, Sin, Sout,
-                       ws->partials1, G, ws->partials2, G, tol, kmax, qk, dkm1, dkm2, x);
+    const MinresGivens g = givens_args(k);
+    MBL_HIP(launch_minres_apply<T>(b, F, g, Qr[k % 3], P, ws->partials1, dfl, st));
+    hipLaunchKernelGGL((k_minres_zqdx<T>), dim3(G), dim3(kWG), lds, st, B, F, precond,
+                       k >= 2 ? (const MinresState*)g.Sprev : (const MinresState*)nullptr,
+                       (const MinresState*)g.Scur, ws->partials1, G, ws->alpha + (k & 1), P,
+                       Z[k & 1], Z[(k + 1) & 1], Qr[(k + 1) % 3], ws->partials2, defl,
+                       ws->partials3, Qr[(k + 2) % 3], D[(k + 1) & 1], D[k & 1], x);
     MBL_HIP(hipGetLastError());
     return MBL_OK;
   };
-  // The buffers of iteration k depend only on k & 1 and every kernel reads its
-  // scalars and done flag from device memory, so kGraphIters iterations are
+  // after the last issued iteration K: its Givens step and its d/x update
+  auto finish = [&](int64_t K, hipStream_t st) -> mbl_status {
+    const MinresGivens g = givens_args(K + 1);
+    hipLaunchKernelGGL(k_minres_givens_last, dim3(1), dim3(kWG), 0, st, g);
+    hipLaunchKernelGGL((k_minres_dx_last<T>), dim3(FG), dim3(kWG), 0, st, n,
+                       (const MinresState*)g.Sprev, (const MinresState*)g.Scur, Qr[K % 3],
+                       D[K & 1], (const T*)D[(K + 1) & 1], x);
+    MBL_HIP(hipGetLastError());
+    return MBL_OK;
+  };
+  // Iteration 1 runs eagerly; then blocks of kGraphIters iterations (2..13,
+  // 14..25, ...), whose buffers and state slots depend only on k mod 6 and
+  // whose kernels read their scalars and done flags from device memory, are
   // captured once (on the workspace's own stream) and replayed on the
   // caller's stream; a replay after convergence is a sequence of no-op
   // launches. The graph holds its kernel arguments (fields and shift, tol,
   // kmax, x, the preconditioner, the deflation vector), so it is captured
   // again when any of them changes.
-  constexpr int64_t kGraphIters = 16;
+  constexpr int64_t kGraphIters = 12;
+  const int64_t kChunkIters = 4 * kGraphIters;
   if (ws->graph_mode < 0) {
     const char* e = getenv("MBL_MINRES_GRAPHS");
     ws->graph_mode = (e && std::string(e) == "0") ? 0 : 1;
   }
-  const bool use_graph = ws->graph_mode == 1 && kmax >= kChunkIters;
+  const bool use_graph = ws->graph_mode == 1 && kmax > kChunkIters;
   const int ti = std::is_same<T, float>::value ? 1 : 0;
   if (use_graph) {
     std::vector<unsigned char> key(sizeof(FieldArgs) + 2 * sizeof(double) + sizeof(int64_t) +
@@ -625,7 +629,7 @@ static mbl_status minres_core(mbl_basis_s* b, const FieldArgs& F, const double* 
       hipGraph_t g = nullptr;
       MBL_HIP(hipStreamBeginCapture(ws->cap, hipStreamCaptureModeThreadLocal));
       mbl_status cst = MBL_OK;
-      for (int64_t k = 1; k <= kGraphIters && cst == MBL_OK; ++k) cst = iteration(k, ws->cap);
+      for (int64_t k = 2; k <= kGraphIters + 1 && cst == MBL_OK; ++k) cst = iteration(k, ws->cap);
       hipError_t ee = hipStreamEndCapture(ws->cap, &g);
       if (cst != MBL_OK) {
         if (g) (void)hipGraphDestroy(g);
@@ -638,6 +642,20 @@ static mbl_status minres_core(mbl_basis_s* b, const FieldArgs& F, const double* 
       ws->graph_key[ti] = key;
     }
   }
+  int64_t issued = 0;
+  int pending = 0;       // status copies in flight (0..2)
+  int slot = 0;
+  bool done = false;
+  // a status copy for the chunk ending at iteration k goes to h_state[slot]
+  auto check = [&](int which) -> mbl_status {
+    MBL_HIP(hipEventSynchronize(ws->ev[which]));
+    if (ws->h_state[which].done) done = true;
+    return MBL_OK;
+  };
+  if (kmax >= 1) {
+    MBL_TRY(iteration(1, s));
+    issued = 1;
+  }
   while (!done && issued < kmax) {
     const int64_t k_end = std::min(kmax, issued + kChunkIters);
     if (use_graph && k_end - issued == kChunkIters) {
@@ -646,9 +664,9 @@ static mbl_status minres_core(mbl_basis_s* b, const FieldArgs& F, const double* 
     } else {
       for (int64_t k = issued + 1; k <= k_end; ++k) MBL_TRY(iteration(k, s));
     }
-    MBL_HIP(hipGetLastError());
     issued = k_end;
-    MBL_HIP(hipMemcpyAsync(&ws->h_state[slot], S + (issued & 1), sizeof(MinresState),
+    // the newest state on the device is the one after iteration issued - 1
+    MBL_HIP(hipMemcpyAsync(&ws->h_state[slot], S + ((issued - 1) & 1), sizeof(MinresState),
                            hipMemcpyDeviceToHost, s));
     MBL_HIP(hipEventRecord(ws->ev[slot], s));
     ++pending;
@@ -658,14 +676,12 @@ static mbl_status minres_core(mbl_basis_s* b, const FieldArgs& F, const double* 
     }
     slot ^= 1;
   }
-  // drain: the most recent status copy is in slot ^ 1
   if (pending > 0) MBL_TRY(check(slot ^ 1));
-  if (!done) {  // issued == kmax without a done flag in the copies (cannot happen) : sync once
-    MBL_HIP(hipMemcpyAsync(&ws->h_state[0], S + (issued & 1), sizeof(MinresState),
-                           hipMemcpyDeviceToHost, s));
-    MBL_HIP(hipStreamSynchronize(s));
-    last = ws->h_state[0];
-  }
+  if (issued >= 1) MBL_TRY(finish(issued, s));
+  MBL_HIP(hipMemcpyAsync(&ws->h_state[0], S + (issued & 1), sizeof(MinresState),
+                         hipMemcpyDeviceToHost, s));
+  MBL_HIP(hipStreamSynchronize(s));
+  const MinresState last = ws->h_state[0];
   *iters = last.k;
   *phi = last.phi;
   if (last.bad) {

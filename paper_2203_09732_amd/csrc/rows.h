@@ -327,4 +327,43 @@ __device__ __forceinline__ void for_rows(const DevBasis& B, const RowTables& t, 
   X(26, 9)                 \
   X(26, 11)
 
+
+// One step of the MINRES scalar recurrence of Alg. 2: from the state after
+// iteration k - 1, alpha_k and q_{k+1} . z_{k+1}, the state after iteration k
+// (beta_{k+1}, the Givens rotation, phi_k, the d/x coefficients of iteration
+// k, done). A done state is carried with a zero step.
+__device__ __forceinline__ MinresState minres_givens_step(const MinresState& si, double alpha,
+                                                          double qz, double tol, int64_t kmax) {
+  MinresState so = si;
+  if (si.done) {
+    so.d_tau = 0.0;
+    return so;
+  }
+  const double beta = si.beta;
+  const double beta_next = sqrt(qz);
+  const double delta = si.c * si.dhat + si.s * alpha;
+  const double gamma_hat = -si.s * si.dhat + si.c * alpha;
+  const double eps_next = si.s * beta_next;
+  const double dhat_next = si.c * beta_next;
+  const double gamma = sqrt(gamma_hat * gamma_hat + beta_next * beta_next);
+  const double c = gamma_hat / gamma;
+  const double s = beta_next / gamma;
+  so.d_inv_beta = 1.0 / beta;
+  so.d_delta = delta;
+  so.d_eps = si.eps;
+  so.d_inv_gamma = 1.0 / gamma;
+  so.d_tau = c * si.phi;
+  so.beta_prev = beta;
+  so.beta = beta_next;
+  so.c = c;
+  so.s = s;
+  so.dhat = dhat_next;
+  so.eps = eps_next;
+  so.phi = -s * si.phi;
+  so.k = si.k + 1;
+  so.bad = !isfinite(so.phi) || !isfinite(alpha) || !isfinite(beta_next);
+  so.done = so.bad || !(fabs(so.phi) >= tol && so.k < kmax);
+  return so;
+}
+
 }  // namespace mbl

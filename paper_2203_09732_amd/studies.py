@@ -4,7 +4,7 @@
   spectral midpoint with the identity, Jacobi and row-norm preconditioners
   (the comparison of Sec. II / Sec. IV A: iterations against L for h = 3, 4).
 * ``memory``: device bytes of a workspace against L, next to the linear model
-  8 n (12 + mmax + 1) and the paper's 8 n (9 + m) (Sec. IV A).
+  8 n (13 + mmax + 1) and the paper's 8 n (9 + m) (Sec. IV A).
 * ``eig``: one full shift-invert Lanczos run (sigma at the spectral midpoint,
   the nev pairs nearest it, MINRES tol 1e-12, eig_tol 1e-10), its time per
   converged eigenpair, steps and MINRES iterations (set MBL_VERBOSE=1 for a
@@ -58,7 +58,7 @@ def memory_curve(Ls, mmax=130):
         b = mbl.Basis(L)
         ws = mbl.Workspace(b, mmax)
         yield {"study": "memory", "L": L, "n": b.n, "mmax": mmax, "workspace_bytes": ws.bytes,
-               "model_8n(12+mmax+1)": 8 * b.n * (12 + mmax + 1),
+               "model_8n(13+mmax+1)": 8 * b.n * (13 + mmax + 1),
                "paper_model_8n(9+m)": 8 * b.n * (9 + mmax)}
         del ws
 
