@@ -39,6 +39,18 @@ __global__ __launch_bounds__(kBWG) void k_bapply(DevBasis B, BatchDev Q, BGivens
   using T2 = typename Pair<T>::type;
   const int R = Q.R;
   extern __shared__ __align__(16) unsigned char smem[];
+  // the Givens step's inputs are loaded before the table fill, so that the
+  // two latencies overlap
+  BPrefetch pf;
+  BState sp{};
+  double al = 0.0;
+  if (GUARD && gv.active) {
+    bprefetch_partials(gv.part2, gv.G, R, pf);
+    if (threadIdx.x < R) {
+      sp = gv.Sprev[threadIdx.x];
+      al = gv.alpha[threadIdx.x];
+    }
+  }
   const BTables t = bsetup(B, Q, smem);
   __syncthreads();
   const uint32_t rs = (uint32_t)t.rsh + (sizeof(T) == 8 ? 3u : 2u);
@@ -48,10 +60,10 @@ __global__ __launch_bounds__(kBWG) void k_bapply(DevBasis B, BatchDev Q, BGivens
   bool live = true;
   if (GUARD) {
     if (gv.active) {
-      const double qz = bsum_partials(gv.part2, gv.G, R, t.red);
+      const double qz = bsum_prefetched(pf, gv.G, R, t.red);
       if (threadIdx.x < R) {
         const int r = threadIdx.x;
-        const BState so = bgivens_step(gv.Sprev[r], gv.alpha[r], qz, gv.tol, gv.kmax);
+        const BState so = bgivens_step(sp, al, qz, gv.tol, gv.kmax);
         if (blockIdx.x == 0) gv.Scur[r] = so;
         t.shared_r[r] = so.done ? 1.0 : 0.0;
       }
@@ -79,10 +91,10 @@ __global__ __launch_bounds__(kBWG) void k_bapply(DevBasis B, BatchDev Q, BGivens
       T2 yv;
       yv.x = (T)(d0 * (double)xv.x + 0.5 * o0);
       yv.y = (T)(d1 * (double)xv.y + 0.5 * o1);
-      if (MODE == 0)
-        BIO<T>::template st<kStoreStream>(yv, ry, ad.jv, ad.sb);
-      else   // the MINRES product is read back by the next kernel
-        BIO<T>::template st<0>(yv, ry, ad.jv, ad.sb);
+      // streaming stores also for the MINRES product: p is far larger than
+      // L2, and stores that allocate there evict the x lines the gathers
+      // reuse (measured: the product, z/q and d/x kernels all run faster)
+      BIO<T>::template st<kStoreStream>(yv, ry, ad.jv, ad.sb);
       if (MODE == 1) {
         acc0 += (double)xv.x * (double)yv.x;
         acc1 += (double)xv.y * (double)yv.y;
@@ -197,11 +209,13 @@ __global__ __launch_bounds__(kBWG) void k_bzq(DevBasis B, BatchDev Q, int kind,
   using T2 = typename Pair<T>::type;
   const int R = Q.R, PR = R >> 1;
   extern __shared__ __align__(16) unsigned char smem[];
+  BPrefetch pf;   // loaded before the table fill (overlapping latencies)
+  bprefetch_partials(part1, G, R, pf);
   const BTables t = bsetup(B, Q, smem);
   __syncthreads();
   // alpha_k = q_k . p_k / beta_k^2 from the product's partials (the same in
   // every workgroup; workgroup 0 keeps it for the Givens step)
-  const double qp = bsum_partials(part1, G, R, t.red);
+  const double qp = bsum_prefetched(pf, G, R, t.red);
   if (threadIdx.x < R) {
     const int r = threadIdx.x;
     const double beta = S[r].beta;

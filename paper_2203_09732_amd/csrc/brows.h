@@ -301,12 +301,8 @@ __device__ __forceinline__ double bblock_sum(double acc0, double acc1, double* r
 // nt / R, ... of realization r = t % R; lanes of one realization inside a
 // wave are combined by a butterfly, then the waves in index order. Thread
 // r < R returns the sum for realization r, the others 0. red: [waves][R].
-__device__ __forceinline__ double bsum_partials(const double* __restrict__ partials, int G, int R,
-                                                double* red) {
-  const int t = threadIdx.x, nt = blockDim.x;
-  const int r = t % R, per = nt / R;
-  double v = 0.0;
-  for (int g = t / R; g < G; g += per) v += partials[(size_t)g * R + r];
+__device__ __forceinline__ double bsum_combine(double v, int R, double* red) {
+  const int t = threadIdx.x;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1)
     if (o >= R) v += __shfl_xor(v, o, 64);
@@ -316,11 +312,45 @@ __device__ __forceinline__ double bsum_partials(const double* __restrict__ parti
   __syncthreads();
   double sum = 0.0;
   if (t < R) {
-    const int nw = nt >> 6;
+    const int nw = (int)blockDim.x >> 6;
     for (int w = 0; w < nw; ++w) sum += red[w * R + t];
   }
   __syncthreads();
   return sum;
+}
+
+__device__ __forceinline__ double bsum_partials(const double* __restrict__ partials, int G, int R,
+                                                double* red) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  const int r = t % R, per = nt / R;
+  double v = 0.0;
+  for (int g = t / R; g < G; g += per) v += partials[(size_t)g * R + r];
+  return bsum_combine(v, R, red);
+}
+
+// bsum_partials split in two for kBWG-thread workgroups: the loads, issued
+// at kernel entry so that their latency overlaps the LDS table fill, and
+// later the same fixed-order sum (G <= kBGrid, R <= kBMaxR).
+constexpr int kBPrefetch = kBGrid * kBMaxR / kBWG;
+struct BPrefetch {
+  double v[kBPrefetch];
+};
+__device__ __forceinline__ void bprefetch_partials(const double* __restrict__ partials, int G,
+                                                   int R, BPrefetch& f) {
+  const int t = threadIdx.x, r = t % R, per = kBWG / R;
+#pragma unroll
+  for (int j = 0; j < kBPrefetch; ++j) {
+    const int g = t / R + j * per;
+    f.v[j] = g < G ? partials[(size_t)g * R + r] : 0.0;
+  }
+}
+__device__ __forceinline__ double bsum_prefetched(const BPrefetch& f, int G, int R, double* red) {
+  const int t = threadIdx.x, per = kBWG / R;
+  double v = 0.0;
+#pragma unroll
+  for (int j = 0; j < kBPrefetch; ++j)
+    if (t / R + j * per < G) v += f.v[j];
+  return bsum_combine(v, R, red);
 }
 
 // One step of the MINRES scalar recurrence of Alg. 2 for one realization:

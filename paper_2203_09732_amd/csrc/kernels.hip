@@ -37,23 +37,32 @@ __global__ __launch_bounds__(kWG) void k_apply(DevBasis B, FieldArgs F, MinresGi
                                                const T* __restrict__ x, T* __restrict__ y,
                                                double* __restrict__ partials, Defl D) {
   extern __shared__ __align__(16) unsigned char smem[];
+  // the MINRES scalars and partial sums are loaded before the table fill, so
+  // that the two latencies overlap
+  PartialsPrefetch pq, pc;
+  MinresState sp{};
+  double al = 0.0;
+  if (GUARD) {
+    if (G.active) {
+      prefetch_partials(G.part2, G.P2, pq);
+      sp = *G.Sprev;
+      al = *G.alpha;
+    } else if (G.Scur->done) {
+      return;
+    }
+    if (D.v) prefetch_partials(D.c_part, D.P, pc);
+  }
   const RowTables t = setup_tables<L>(B, F, smem);
   __syncthreads();
-  if (GUARD) {
-    bool done;
-    if (G.active) {
-      const double qz = reduce_partials(G.part2, G.P2, t.red);
-      const MinresState so = minres_givens_step(*G.Sprev, *G.alpha, qz, G.tol, G.kmax);
-      if (blockIdx.x == 0 && threadIdx.x == 0) *G.Scur = so;
-      done = so.done != 0;
-    } else {
-      done = G.Scur->done != 0;
-    }
-    if (done) return;
+  if (GUARD && G.active) {
+    const double qz = reduce_prefetched(pq, G.P2, t.red);
+    const MinresState so = minres_givens_step(sp, al, qz, G.tol, G.kmax);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *G.Scur = so;
+    if (so.done) return;
   }
   // rank-one term theta v (v . x) of a deflated MINRES operator
   double dcoef = 0.0;
-  if (GUARD && D.v) dcoef = D.theta * reduce_partials(D.c_part, D.P, t.red);
+  if (GUARD && D.v) dcoef = D.theta * reduce_prefetched(pc, D.P, t.red);
   double acc = 0.0;
   for_rows(B, t, [&](uint32_t row, uint32_t hi, uint32_t lo, uint32_t j, uint32_t block0,
                      uint32_t a) {

@@ -103,11 +103,13 @@ __global__ __launch_bounds__(kWG) void k_minres_zqdx(
   const bool dx = Sprev && !Sprev->done;       // iteration k - 1 was taken
   if (!zq && !dx) return;
   extern __shared__ __align__(16) unsigned char smem[];
+  PartialsPrefetch pp;   // loaded before the table fill (overlapping latencies)
+  if (zq) prefetch_partials(part1, P1, pp);
   const RowTables t = setup_tables(B, F, smem);
   const MinresState sc = *Scur;
   double alpha = 0.0;
   if (zq) {
-    const double qp = reduce_partials(part1, P1, t.red);
+    const double qp = reduce_prefetched(pp, P1, t.red);
     alpha = qp / (sc.beta * sc.beta);
     if (blockIdx.x == 0 && threadIdx.x == 0) *alpha_out = alpha;
   } else {

@@ -49,6 +49,29 @@ __device__ __forceinline__ double reduce_partials(const double* __restrict__ p, 
   return block_sum_all(v, red);
 }
 
+// reduce_partials split in two for kWG-thread workgroups: the loads, issued
+// at kernel entry so that their latency overlaps the LDS table fill, and
+// later the same fixed-order sum (P <= kMaxPartials)
+struct PartialsPrefetch {
+  double v[kMaxPartials / kWG];
+};
+__device__ __forceinline__ void prefetch_partials(const double* __restrict__ p, int P,
+                                                  PartialsPrefetch& f) {
+#pragma unroll
+  for (int j = 0; j < kMaxPartials / kWG; ++j) {
+    const int i = (int)threadIdx.x + j * kWG;
+    f.v[j] = i < P ? p[i] : 0.0;
+  }
+}
+__device__ __forceinline__ double reduce_prefetched(const PartialsPrefetch& f, int P,
+                                                    double* red) {
+  double v = 0.0;
+#pragma unroll
+  for (int j = 0; j < kMaxPartials / kWG; ++j)
+    if ((int)threadIdx.x + j * kWG < P) v += f.v[j];
+  return block_sum_all(v, red);
+}
+
 constexpr int kLdsLut = 128;   // doubles: field table, 16 entries per nibble, 8 nibbles
 constexpr int kLdsRed = 16;    // doubles: reduction scratch (up to 16 waves)
 
