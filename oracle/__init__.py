@@ -19,10 +19,12 @@ Every routine is a slow, direct statement of what the paper defines:
                  eigenpairs nearest sigma;
 * ``twist``    - the twist overlap z = <psi|U_twist|psi> (Sec. III, App. B);
 * ``adjoint``  - Hellmann-Feynman energies' derivatives and eigenvector
-                 derivatives by the first-order perturbation sum.
+                 derivatives by the first-order perturbation sum;
+* ``observables`` - the bipartite entanglement entropy (Schmidt
+                 decomposition) and the level-spacing ratio (Sec. IV).
 
 Conventions fixed here (the paper leaves them open): site j = 1..L is bit
 j-1 of the state integer, a set bit is S^z = +1/2, the basis is in ascending
 integer order, J = 1.
 """
-from . import model, precond, minres, lanczos, twist, adjoint  # noqa: F401
+from . import model, precond, minres, lanczos, twist, adjoint, observables  # noqa: F401
