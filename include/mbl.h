@@ -185,6 +185,29 @@ mbl_status mbl_eig_residual(mbl_basis b, const double* h_host, const double* E_h
                             const double* psi_dev, int64_t ld, int nvec,
                             double* resid_host, void* stream);
 
+/* ---- bipartite entanglement entropy (Sec. IV, entanglement and level
+ * spacing): S_t = -Tr rho_A ln rho_A for each of nvec real vectors psi_dev
+ * (device, n x nvec column-major, ld >= n; any norm: rho_A is divided by its
+ * trace), with A = sites 1..la (bits 0..la-1), 1 <= la <= L-1 (the paper
+ * takes la = L/2). rho_A is block diagonal in the number k of up spins in
+ * A; the coefficients of each block are gathered on the device and their
+ * Gram matrices (min(C(la,k), C(L-la,L/2-k)) squared) formed on the FP64
+ * matrix cores; the eigenvalues of the blocks are found on the host
+ * (Householder tridiagonalisation, implicit QL) with up to 16 threads.
+ * S_host[nvec]. Allocates device scratch of at most 4 GiB (16 n bytes per
+ * vector of a pass) and frees it before returning. Synchronizes stream.
+ * MBL_ERR_NUMERIC for a zero or non-finite vector. */
+mbl_status mbl_entanglement_entropy(mbl_basis b, const double* psi_dev, int64_t ld, int nvec,
+                                    int la, double* S_host, void* stream);
+
+/* ---- level-spacing ratio (Sec. IV): over the ascending sort of
+ * evals_host[count] (count >= 3), r_k = min(d_k, d_{k-1}) / max(d_k, d_{k-1})
+ * with d_k = E_{k+1} - E_k. r_host[count-2] (may be NULL) receives r_1 ..
+ * r_{count-2}, NaN where both spacings are 0; *r_mean is the mean of the
+ * defined ratios (NaN if none). Host only. */
+mbl_status mbl_spacing_ratio(int count, const double* evals_host, double* r_host,
+                             double* r_mean);
+
 /* ---- sigma = (E_min + E_max) / 2 (Sec. IV A) by Lanczos on H without
  * reorthogonalisation (the extremal Ritz values converge first and are not
  * affected by the copies loss of orthogonality creates), from a seeded start

@@ -78,6 +78,8 @@ _sig("mbl_minres_solve", _i32, [_vp, _dp, _d, _vp, _vp, _d, _i64, C.c_int, C.c_i
 _sig("mbl_si_lanczos", _i32, [_vp, _dp, _d, C.c_int, C.c_int, _d, _i64, _d, _d, _d, _vp, _u64,
                               C.c_int, C.c_int, _vp, _dp, _vp, _i64, _dp, C.POINTER(SiInfo), _vp])
 _sig("mbl_twist_expect", _i32, [_vp, _vp, _i64, C.c_int, _dp, _vp])
+_sig("mbl_entanglement_entropy", _i32, [_vp, _vp, _i64, C.c_int, C.c_int, _dp, _vp])
+_sig("mbl_spacing_ratio", _i32, [C.c_int, _dp, _dp, _dp])
 _sig("mbl_eig_residual", _i32, [_vp, _dp, _dp, _vp, _i64, C.c_int, _dp, _vp])
 _sig("mbl_sigma_midpoint", _i32, [_vp, _dp, _d, C.c_int, _dp, _dp, _dp, _vp])
 _sig("mbl_dot", _i32, [_i64, _vp, _vp, _dp, _vp])
@@ -302,6 +304,33 @@ def twist_expect(basis: Basis, psi, stream=None) -> np.ndarray:
     _check(lib.mbl_twist_expect(basis.handle, _ptr(store), basis.n, nvec, z.ctypes.data_as(_dp),
                                 _stream(stream)), "mbl_twist_expect")
     return z[0::2] + 1j * z[1::2]
+
+
+def entanglement_entropy(basis: Basis, psi, la: int | None = None, stream=None) -> np.ndarray:
+    """S_t = -Tr rho_A ln rho_A, A = sites 1..la (default L/2), for the
+    columns of psi (n,) or (n, nvec) (Sec. IV)."""
+    import torch
+    if psi.dim() == 1:
+        psi = psi[:, None]
+    store = psi.t().contiguous() if not psi.t().is_contiguous() else psi.t()
+    _need_cuda(store, torch.float64, None, "psi")
+    nvec = store.shape[0]
+    S = np.zeros(nvec)
+    la = basis.L // 2 if la is None else int(la)
+    _check(lib.mbl_entanglement_entropy(basis.handle, _ptr(store), basis.n, nvec, la,
+                                        S.ctypes.data_as(_dp), _stream(stream)),
+           "mbl_entanglement_entropy")
+    return S
+
+
+def spacing_ratio(evals):
+    """(mean r, r_k) of the level-spacing ratios of the sorted eigenvalues (Sec. IV)."""
+    E, Ep = _f64(np.ravel(evals))
+    r = np.zeros(max(len(E) - 2, 1))
+    mean = C.c_double()
+    _check(lib.mbl_spacing_ratio(len(E), Ep, r.ctypes.data_as(_dp), C.byref(mean)),
+           "mbl_spacing_ratio")
+    return mean.value, r[:len(E) - 2]
 
 
 def eig_residual(basis: Basis, h, E, psi, stream=None) -> np.ndarray:

@@ -26,7 +26,8 @@ COMMON = [
     "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas",
 ]
 
-SOURCES = ["kernels.hip", "minres.hip", "lanczos.hip", "batched.hip", "adjoint.hip", "api.hip"]
+SOURCES = ["kernels.hip", "minres.hip", "lanczos.hip", "batched.hip", "adjoint.hip", "schmidt.hip",
+           "api.hip"]
 
 
 def _compile(src: str) -> str:

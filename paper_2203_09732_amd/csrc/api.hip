@@ -46,6 +46,10 @@ mbl_status twist_run(mbl_basis_s* b, mbl_workspace_s* ws, const double* psi, int
 mbl_status eig_residual_run(mbl_basis_s* b, mbl_workspace_s* ws, const double* h,
                             const double* E, const double* psi, int64_t ld, int nvec,
                             double* resid, hipStream_t s);
+// declared in schmidt.hip
+mbl_status entropy_run(mbl_basis_s* b, const double* psi, int64_t ld, int nvec, int la,
+                       double* S, hipStream_t s);
+mbl_status spacing_ratio_run(int count, const double* E, double* r, double* r_mean);
 
 static uint64_t binom(int n, int k) {
   if (k < 0 || k > n) return 0;
@@ -477,6 +481,24 @@ mbl_status mbl_twist_expect(mbl_basis b, const double* psi_dev, int64_t ld, int 
   std::unique_lock<std::mutex> lk;
   MBL_TRY(with_scratch(b, &ws, &lk));
   return twist_run(b, ws, psi_dev, ld, nvec, z_host, S(stream));
+}
+
+mbl_status mbl_entanglement_entropy(mbl_basis b, const double* psi_dev, int64_t ld, int nvec,
+                                    int la, double* S_host, void* stream) {
+  clear_error();
+  MBL_ARG(b && psi_dev && S_host, "NULL argument");
+  MBL_ARG(nvec >= 1 && ld >= b->n, "need nvec >= 1 and ld >= n");
+  MBL_ARG(la >= 1 && la <= b->L - 1, "need 1 <= la <= L - 1");
+  return entropy_run(b, psi_dev, ld, nvec, la, S_host, S(stream));
+}
+
+mbl_status mbl_spacing_ratio(int count, const double* evals_host, double* r_host,
+                             double* r_mean) {
+  clear_error();
+  MBL_ARG(evals_host && r_mean, "NULL argument");
+  MBL_ARG(count >= 3, "need at least 3 eigenvalues");
+  for (int i = 0; i < count; ++i) MBL_ARG(std::isfinite(evals_host[i]), "non-finite eigenvalue");
+  return spacing_ratio_run(count, evals_host, r_host, r_mean);
 }
 
 mbl_status mbl_eig_residual(mbl_basis b, const double* h_host, const double* E_host,

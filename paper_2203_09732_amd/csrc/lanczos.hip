@@ -114,12 +114,15 @@ static int lgrid(int64_t n) {
 // Wilkinson-type shift from the leading 2 x 2 block, accumulating the
 // rotations into the eigenvector matrix (Golub & Van Loan, Sec. 8.3).
 // alpha[0..k-1] diagonal, beta[0..k-2] off-diagonal. evals ascending,
-// evecs k x k column-major (column i belongs to evals[i]). Returns 0 on
-// success, -1 if an eigenvalue needed more than 60 iterations.
+// evecs k x k column-major (column i belongs to evals[i]); with evecs NULL
+// only the eigenvalues are formed. Returns 0 on success, -1 if an eigenvalue
+// needed more than 60 iterations.
 int tridiag_eig(int k, const double* alpha, const double* beta, double* evals, double* evecs) {
-  std::vector<double> d(alpha, alpha + k), e(k, 0.0), Z((size_t)k * k, 0.0);
+  const bool vec = evecs != nullptr;
+  std::vector<double> d(alpha, alpha + k), e(k, 0.0), Z(vec ? (size_t)k * k : 0, 0.0);
   for (int i = 0; i + 1 < k; ++i) e[i] = beta[i];
-  for (int i = 0; i < k; ++i) Z[(size_t)i * k + i] = 1.0;
+  if (vec)
+    for (int i = 0; i < k; ++i) Z[(size_t)i * k + i] = 1.0;
   for (int l = 0; l < k; ++l) {
     int iter = 0;
     for (;;) {
@@ -155,6 +158,7 @@ int tridiag_eig(int k, const double* alpha, const double* beta, double* evals, d
         p = s * r;
         d[i + 1] = g + p;
         g = c * r - b;
+        if (!vec) continue;
         double* zi = &Z[(size_t)i * k];
         double* zi1 = &Z[(size_t)(i + 1) * k];
         for (int row = 0; row < k; ++row) {
@@ -174,7 +178,8 @@ int tridiag_eig(int k, const double* alpha, const double* beta, double* evals, d
   std::sort(order.begin(), order.end(), [&](int a, int b) { return d[a] < d[b]; });
   for (int i = 0; i < k; ++i) {
     evals[i] = d[order[i]];
-    std::copy(&Z[(size_t)order[i] * k], &Z[(size_t)order[i] * k] + k, &evecs[(size_t)i * k]);
+    if (vec)
+      std::copy(&Z[(size_t)order[i] * k], &Z[(size_t)order[i] * k] + k, &evecs[(size_t)i * k]);
   }
   return 0;
 }

@@ -98,3 +98,25 @@ def test_single_hip_runtime_in_process():
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=120)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip().splitlines()[-1] == "1"
+
+
+def test_spacing_ratio_matches_oracle(mbl):
+    """Host-only level-spacing ratio (Sec. IV) against the oracle's."""
+    from oracle import observables
+    rng = np.random.default_rng(3)
+    for n in (3, 4, 17, 500):
+        E = rng.standard_normal(n)
+        mean, r = mbl.spacing_ratio(E)
+        want = observables.spacing_ratios(E)
+        assert np.allclose(r, want, rtol=0, atol=1e-15)
+        assert abs(mean - observables.mean_spacing_ratio(E)) <= 1e-15
+    mean, r = mbl.spacing_ratio([0.0, 1.0, 1.0, 1.0, 2.0])
+    assert np.isnan(r[1]) and r[0] == 0.0 and r[2] == 0.0 and mean == 0.0
+    mean, r = mbl.spacing_ratio([2.0, 2.0, 2.0])
+    assert np.isnan(mean)
+
+
+def test_spacing_ratio_rejects_bad_input(mbl):
+    for E in ([1.0, 2.0], [0.0, np.nan, 1.0, 2.0], [0.0, np.inf, 1.0]):
+        with pytest.raises(mbl.MblError):
+            mbl.spacing_ratio(E)

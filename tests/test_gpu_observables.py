@@ -1,0 +1,114 @@
+"""Entanglement entropy (Sec. IV) on the device against the oracle's
+Schmidt decomposition, and the level-spacing ratio through the library."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import model, observables
+from workloads import disorder_fields, gaussian_vector
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available()
+    return t
+
+
+def dev(torch, a):
+    return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+
+
+@pytest.mark.parametrize("L", [4, 6, 8, 10])
+def test_entropy_every_cut_small(gpu, torch, L):
+    """Random vectors (three at once), every cut 1..L-1, against the oracle."""
+    say(f"entropy L={L} every cut")
+    b = gpu.Basis(L)
+    V = np.stack([gaussian_vector(b.n, 60 + t) for t in range(3)], axis=1)
+    Vd = dev(torch, V)
+    for la in range(1, L):
+        S = gpu.entanglement_entropy(b, Vd, la)
+        want = [observables.entanglement_entropy(L, V[:, t], la) for t in range(3)]
+        assert np.abs(S - want).max() <= 1e-11, (la, S, want)
+
+
+@pytest.mark.parametrize("L,las", [(12, (1, 4, 6, 9)), (14, (3, 7, 12)), (16, (5, 8)),
+                                   (18, (9,)), (20, (7, 10))])
+def test_entropy_larger_sizes(gpu, torch, L, las):
+    say(f"entropy L={L} cuts {las}")
+    b = gpu.Basis(L)
+    v = gaussian_vector(b.n, 70 + L)
+    vd = dev(torch, v)
+    for la in las:
+        S = gpu.entanglement_entropy(b, vd, la)[0]
+        want = observables.entanglement_entropy(L, v, la)
+        assert abs(S - want) <= 1e-10, (la, S, want)
+
+
+@pytest.mark.parametrize("L", [8, 12, 16])
+def test_entropy_closed_forms(gpu, torch, L):
+    """Mirror singlets: S = min(la, L-la) ln 2; one basis state: S = 0; the
+    uniform vector: the entropy of the hypergeometric block weights."""
+    say(f"entropy closed forms L={L}")
+    b = gpu.Basis(L)
+    states = model.sector_states(L)
+    pairs = [(j, L + 1 - j) for j in range(1, L // 2 + 1)]
+    amps = {}
+    for choice in range(1 << len(pairs)):
+        s, a = 0, 1.0
+        for t, (i, j) in enumerate(pairs):
+            s |= 1 << ((j if (choice >> t) & 1 else i) - 1)
+            a *= (-1 if (choice >> t) & 1 else 1) / math.sqrt(2)
+        amps[s] = a
+    sing = np.zeros(b.n)
+    sing[np.searchsorted(states, list(amps))] = list(amps.values())
+    one = np.zeros(b.n)
+    one[b.n // 3] = 1.0
+    uni = np.full(b.n, 2.5)
+    V = dev(torch, np.stack([sing, one, uni], axis=1))
+    for la in (1, L // 2 - 1, L // 2, L - 2):
+        S = gpu.entanglement_entropy(b, V, la)
+        p = [math.comb(la, k) * math.comb(L - la, L // 2 - k) / b.n for k in range(la + 1)
+             if 0 <= L // 2 - k <= L - la]
+        hyper = -sum(q * math.log(q) for q in p if q > 0)
+        assert abs(S[0] - min(la, L - la) * math.log(2)) <= 1e-11
+        assert abs(S[1]) <= 1e-12
+        assert abs(S[2] - hyper) <= 1e-11
+
+
+def test_entropy_of_eigenvectors_L14(gpu, torch):
+    """Mid-spectrum eigenvectors from the library's shift-invert Lanczos:
+    the entropies equal the oracle's on the same vectors, and at h = 0.5
+    (ergodic side) their mean is within 0.5 of Eq. (ee_random)."""
+    L = 14
+    say("entropy of SI-Lanczos eigenvectors L=14")
+    b = gpu.Basis(L)
+    h = disorder_fields(L, 0.5, 3)
+    lo, hi, sigma = gpu.sigma_midpoint(b, h, 1e-10)
+    res = gpu.si_lanczos(b, h, sigma, nev=6, escale=max(abs(lo), abs(hi)))
+    U = res.evecs
+    S = gpu.entanglement_entropy(b, U)
+    Uh = U.detach().cpu().numpy()
+    want = [observables.entanglement_entropy(L, Uh[:, t]) for t in range(Uh.shape[1])]
+    assert np.abs(S - want).max() <= 1e-10
+    assert abs(np.mean(S) - observables.rmt_entropy(L)) < 0.5
+
+
+def test_entropy_errors(gpu, torch):
+    b = gpu.Basis(8)
+    v = dev(torch, np.zeros(b.n))
+    with pytest.raises(gpu.MblError):
+        gpu.entanglement_entropy(b, v, 4)          # zero vector
+    w = dev(torch, gaussian_vector(b.n, 1))
+    for la in (0, 8):
+        with pytest.raises(gpu.MblError):
+            gpu.entanglement_entropy(b, w, la)
