@@ -5,6 +5,12 @@
   (the comparison of Sec. II / Sec. IV A: iterations against L for h = 3, 4).
 * ``memory``: device bytes of a workspace against L, next to the linear model
   8 n (13 + mmax + 1) and the paper's 8 n (9 + m) (Sec. IV A).
+* ``scan``: the disorder scan of Sec. IV: for each (L, h), R realizations
+  solved together in the batched form (the nev pairs nearest each one's
+  spectral midpoint), then per realization the mean level-spacing ratio,
+  the mean half-chain entanglement entropy and the mean |z|^2 over its
+  eigenstates; the row reports their mean and standard deviation over
+  realizations, next to the GOE and Poisson ratios and Eq. (ee_random).
 * ``eig``: one full shift-invert Lanczos run (sigma at the spectral midpoint,
   the nev pairs nearest it, MINRES tol 1e-12, eig_tol 1e-10), its time per
   converged eigenpair, steps and MINRES iterations (set MBL_VERBOSE=1 for a
@@ -90,21 +96,75 @@ def eigen_run(L, h, seed, nev, precision="fp64"):
            "evals": [float(e) for e in res.evals], "abs_z": [float(abs(v)) for v in z]}
 
 
+def disorder_scan(Ls, hs, R=32, nev=20, first_seed=0):
+    import math
+
+    import numpy as np
+    import torch
+
+    import paper_2203_09732_amd as mbl
+    from paper_2203_09732_amd import tune
+    from workloads import disorder_fields
+    for L in Ls:
+        b = mbl.Basis(L, tune.best_lo_bits(L, R, "fp64"))
+        mmax = min(b.n, 3 * nev + 40)
+        bt = mbl.Batch(b, R, mmax=mmax, nevmax=nev)
+        for h in hs:
+            fields = [disorder_fields(L, h, first_seed + r) for r in range(R)]
+            t0 = time.perf_counter()
+            sig, esc = [], []
+            for f in fields:
+                lo, hi, sg = mbl.sigma_midpoint(b, f, 1e-12)
+                sig.append(sg)
+                esc.append(max(abs(lo), abs(hi)))
+            res = mbl.si_lanczos_batched(b, bt, fields, sig, nev, mmax=mmax, escale=esc,
+                                         seed=first_seed)
+            z = mbl.twist_expect_batched(b, bt, res.evecs)
+            rr, ss, zz = [], [], []
+            for r in range(R):
+                # the converged pairs (explicit residual within eig_tol * escale)
+                idx = np.nonzero(res.resid[r] <= 1e-10 * esc[r])[0]
+                k = len(idx)
+                rr.append(mbl.spacing_ratio(res.evals[r][idx])[0] if k >= 3 else float("nan"))
+                if k:
+                    U = res.evecs[torch.as_tensor(idx, device=res.evecs.device), :, r].t()
+                    ss.append(float(np.mean(mbl.entanglement_entropy(b, U))))
+                    zz.append(float(np.mean(np.abs(z[r][idx]) ** 2)))
+                else:
+                    ss.append(float("nan"))
+                    zz.append(float("nan"))
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            rr, ss, zz = np.array(rr), np.array(ss), np.array(zz)
+            yield {"study": "scan", "L": L, "n": b.n, "h": h, "R": R, "nev": nev,
+                   "nconv_min": int(res.nconv.min()), "seconds": round(dt, 1),
+                   "r_mean": float(np.nanmean(rr)), "r_std": float(np.nanstd(rr)),
+                   "r_goe": 0.5307, "r_poisson": 2 * math.log(2) - 1,
+                   "S_mean": float(np.nanmean(ss)), "S_std": float(np.nanstd(ss)),
+                   "S_rmt": float(0.5 * math.log(2) * L + 0.5 * math.log(0.5) - 0.25),
+                   "z2_mean": float(np.nanmean(zz)), "z2_std": float(np.nanstd(zz)),
+                   "two_over_n": 2.0 / b.n}
+        del bt
+
+
 def main(argv=None):
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["precond", "memory", "eig"])
+    ap.add_argument("study", choices=["precond", "memory", "eig", "scan"])
     ap.add_argument("--L", type=int, nargs="+", default=[12, 14, 16, 18])
     ap.add_argument("--h", type=float, nargs="+", default=[3.0, 4.0])
     ap.add_argument("--seeds", type=int, nargs="+", default=[0, 1])
     ap.add_argument("--mmax", type=int, default=130)
     ap.add_argument("--nev", type=int, default=4)
     ap.add_argument("--precision", default="fp64")
+    ap.add_argument("--R", type=int, default=32)
     a = ap.parse_args(argv)
     if a.study == "precond":
         rows = precond_iterations(a.L, a.h, a.seeds)
     elif a.study == "memory":
         rows = memory_curve(a.L, a.mmax)
+    elif a.study == "scan":
+        rows = disorder_scan(a.L, a.h, a.R, a.nev, a.seeds[0])
     else:
         rows = (r for L in a.L for r in eigen_run(L, a.h[0], a.seeds[0], a.nev, a.precision))
     for r in rows:
