@@ -121,7 +121,13 @@ __global__ __launch_bounds__(kWG) void k_schmidt_gram(SchmidtArgs A, const uint4
 // ---------------------------------------------------------------------------
 // host: eigenvalues of a symmetric matrix (row-major, overwritten) by
 // Householder reduction to tridiagonal form (Golub & Van Loan, Sec. 8.3.1),
-// then the implicit QL iterations of tridiag_eig without eigenvectors.
+// then the implicit QL iterations of tridiag_eig without eigenvectors. A
+// column whose entries are all below 1e-20 max|A| is taken as zero (the
+// eigenvalues move by less than that); otherwise a rank-deficient block is
+// reduced to a tridiagonal graded down into the subnormal range, where the
+// QL deflation test no longer works. The reduction leaves the large entries
+// at the top of the tridiagonal; it is handed to QL reversed (the same
+// eigenvalues), large entries last, the grading QL converges on.
 static int sym_eigenvalues(int m, std::vector<double>& A, std::vector<double>& w) {
   w.assign(m, 0.0);
   if (m == 1) {
@@ -129,42 +135,54 @@ static int sym_eigenvalues(int m, std::vector<double>& A, std::vector<double>& w
     return 0;
   }
   std::vector<double> d(m), e(m, 0.0), v(m), p(m);
+  double amax = 0.0;
+  for (double x : A) amax = std::max(amax, std::fabs(x));
+  const double negligible = 1e-20 * amax;
   for (int k = 0; k + 2 < m; ++k) {
-    double xx = 0.0;
-    for (int i = k + 1; i < m; ++i) xx += A[(size_t)i * m + k] * A[(size_t)i * m + k];
     d[k] = A[(size_t)k * m + k];
-    if (xx == 0.0) {
+    // the column below the diagonal, scaled by its largest entry so that
+    // neither its norm nor the reflector overflows or underflows
+    double sc = 0.0;
+    for (int i = k + 1; i < m; ++i) sc = std::max(sc, std::fabs(A[(size_t)i * m + k]));
+    if (sc <= negligible) {
       e[k] = 0.0;
       continue;
     }
-    const double xn = std::sqrt(xx), x0 = A[(size_t)(k + 1) * m + k];
-    const double r = x0 >= 0.0 ? -xn : xn;   // H x = r e_1
-    for (int i = k + 1; i < m; ++i) v[i] = A[(size_t)i * m + k];
+    double xx = 0.0;
+    for (int i = k + 1; i < m; ++i) {
+      v[i] = A[(size_t)i * m + k] / sc;
+      xx += v[i] * v[i];
+    }
+    const double xn = std::sqrt(xx);
+    const double r = v[k + 1] >= 0.0 ? -xn : xn;   // H x = r sc e_1
     v[k + 1] -= r;
-    double vtv = 0.0;
-    for (int i = k + 1; i < m; ++i) vtv += v[i] * v[i];
-    // trailing block B <- H B H, H = I - 2 v v^T / v^T v:
-    // p = 2 B v / v^T v, w = p - (v^T p / v^T v) v, B -= v w^T + w v^T
+    double vn = 0.0;
+    for (int i = k + 1; i < m; ++i) vn += v[i] * v[i];
+    vn = std::sqrt(vn);
+    for (int i = k + 1; i < m; ++i) v[i] /= vn;    // unit reflector: H = I - 2 v v^T
+    // trailing block B <- H B H: p = 2 B v, w = p - (v^T p) v, B -= v w^T + w v^T
     double vp = 0.0;
     for (int i = k + 1; i < m; ++i) {
       const double* Ai = &A[(size_t)i * m];
-      double s = 0.0;
-      for (int j = k + 1; j < m; ++j) s += Ai[j] * v[j];
-      p[i] = 2.0 * s / vtv;
+      double sum = 0.0;
+      for (int j = k + 1; j < m; ++j) sum += Ai[j] * v[j];
+      p[i] = 2.0 * sum;
       vp += v[i] * p[i];
     }
-    const double K = vp / vtv;
-    for (int i = k + 1; i < m; ++i) p[i] -= K * v[i];
+    for (int i = k + 1; i < m; ++i) p[i] -= vp * v[i];
     for (int i = k + 1; i < m; ++i) {
       double* Ai = &A[(size_t)i * m];
       const double vi = v[i], pi = p[i];
       for (int j = k + 1; j < m; ++j) Ai[j] -= vi * p[j] + pi * v[j];
     }
-    e[k] = r;
+    e[k] = r * sc;
   }
   d[m - 2] = A[(size_t)(m - 2) * m + (m - 2)];
   e[m - 2] = A[(size_t)(m - 1) * m + (m - 2)];
+  if (std::fabs(e[m - 2]) <= negligible) e[m - 2] = 0.0;
   d[m - 1] = A[(size_t)(m - 1) * m + (m - 1)];
+  std::reverse(d.begin(), d.end());
+  std::reverse(e.begin(), e.begin() + (m - 1));
   return tridiag_eig(m, d.data(), e.data(), w.data(), nullptr);
 }
 

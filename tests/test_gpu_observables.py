@@ -112,3 +112,22 @@ def test_entropy_errors(gpu, torch):
     for la in (0, 8):
         with pytest.raises(gpu.MblError):
             gpu.entanglement_entropy(b, w, la)
+
+
+def test_entropy_nearly_product_states(gpu, torch):
+    """Localised states: one or two basis states plus 1e-150 noise. Their
+    Schmidt blocks have columns 1e-150 below the rest, which the host
+    reduction must scale; S = 0 and S = ln 2 (the two states differ on both
+    sides of the cut)."""
+    L = 12
+    say("entropy of nearly product states")
+    b = gpu.Basis(L)
+    states = model.sector_states(L)
+    noise = 1e-150 * gaussian_vector(b.n, 5)
+    v1 = noise.copy()
+    v1[100] = 1.0
+    a, c = 0b000111 | (0b111000 << 6), 0b111000 | (0b000111 << 6)
+    v2 = noise.copy()
+    v2[np.searchsorted(states, [a, c])] = 1.0 / math.sqrt(2)
+    S = gpu.entanglement_entropy(b, dev(torch, np.stack([v1, v2], axis=1)))
+    assert abs(S[0]) <= 1e-12 and abs(S[1] - math.log(2)) <= 1e-12
