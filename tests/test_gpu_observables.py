@@ -131,3 +131,22 @@ def test_entropy_nearly_product_states(gpu, torch):
     v2[np.searchsorted(states, [a, c])] = 1.0 / math.sqrt(2)
     S = gpu.entanglement_entropy(b, dev(torch, np.stack([v1, v2], axis=1)))
     assert abs(S[0]) <= 1e-12 and abs(S[1] - math.log(2)) <= 1e-12
+
+
+def test_entropy_leading_dimension_through_the_abi(gpu, torch):
+    """Column-major storage with ld = n + 5 (padding poisoned with NaN),
+    called through the C ABI: the padding is never read."""
+    import ctypes as C
+    L = 10
+    b = gpu.Basis(L)
+    ld, nvec = b.n + 5, 3
+    V = np.full((nvec, ld), np.nan)
+    for t in range(nvec):
+        V[t, :b.n] = gaussian_vector(b.n, 90 + t)
+    Vd = dev(torch, V)
+    S = np.zeros(nvec)
+    st = gpu.lib.mbl_entanglement_entropy(b.handle, C.c_void_p(Vd.data_ptr()), ld, nvec, 4,
+                                          S.ctypes.data_as(C.POINTER(C.c_double)), None)
+    assert st == 0
+    want = [observables.entanglement_entropy(L, V[t, :b.n], 4) for t in range(nvec)]
+    assert np.abs(S - want).max() <= 1e-11
