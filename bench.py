@@ -247,6 +247,8 @@ def largest_leg(mbl, torch, steps=20):
     progress(f"largest L=26: batched R=16 apply {us:.1f} us")
     rhs = (X[:, 0] / X[:, 0].norm()).contiguous()
     for prec in ("fp64", "fp32_inner"):
+        mbl.minres_solve(b, h, sigma, rhs, torch.zeros_like(rhs), tol=1e-300, kmax=200,
+                         precision=prec, ws=ws)      # warm-up (graph capture)
         x = torch.zeros_like(rhs)
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -257,6 +259,7 @@ def largest_leg(mbl, torch, steps=20):
                                         "us_per_iter": round(dt / max(info.iters, 1) * 1e6, 2)}
         progress(f"largest L=26: minres single {prec} {dt / max(info.iters, 1) * 1e6:.1f} us/iter")
     Bn = (X / X.norm(dim=0, keepdim=True)).contiguous()
+    mbl.minres_solve_batched(b, bt, fields, sig, Bn, tol=1e-300, kmax=32)   # warm-up
     torch.cuda.synchronize()
     t = time.perf_counter()
     _, its, _, _ = mbl.minres_solve_batched(b, bt, fields, sig, Bn, tol=1e-300, kmax=32)
@@ -386,6 +389,10 @@ def main():
     minres = {}
     rhs = (X[:, 0] / X[:, 0].norm()).contiguous()
     for prec in ("fp64", "fp32_inner"):
+        # a warm-up solve with the same arguments: the iteration blocks are
+        # captured as a graph keyed on them, once per workspace
+        mbl.minres_solve(basis, fields[0], sigmas[0], rhs, torch.zeros_like(rhs), tol=1e-300,
+                         kmax=args.minres_iters, precision=prec, ws=ws)
         x = torch.zeros_like(rhs)
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -399,6 +406,8 @@ def main():
                                     "us_per_realization_iter": round(dt / max(info.iters, 1) * 1e6, 2)}
     Bn = (X / X.norm(dim=0, keepdim=True)).contiguous()
     for prec in ("fp64", "fp32_inner"):
+        mbl.minres_solve_batched(basis, batch, fields, sigmas, Bn, tol=1e-300,
+                                 kmax=max(1, args.minres_iters // 10), precision=prec)
         torch.cuda.synchronize()
         t = time.perf_counter()
         _, its, _, _ = mbl.minres_solve_batched(basis, batch, fields, sigmas, Bn, tol=1e-300,
