@@ -25,6 +25,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstdlib>
 #include <string>
 #include <vector>
@@ -720,6 +721,8 @@ mbl_status minres_run(mbl_basis_s* b, const double* h_host, double sigma, const 
     const double eta = 1e-3;
     const double kMinCycleGain = 10.0;
     const int max_restarts = 60;
+    // MBL_VERBOSE=1: one line per cycle on stderr
+    const bool verbose = std::getenv("MBL_VERBOSE") != nullptr;
     int64_t total = 0;
     int restarts = 0;
     double rM = 0.0, rM_prev = INFINITY;
@@ -732,6 +735,9 @@ mbl_status minres_run(mbl_basis_s* b, const double* h_host, double sigma, const 
       MBL_TRY(reduce_to_host(ws, ws->partials1, np, 2, 2, sums, s));
       rM = std::sqrt(sums[0]);
       first = false;
+      if (verbose)
+        std::fprintf(stderr, "[mbl] fp32-inner cycle %d: ||r||_M^-1 = %.3e after %lld iterations\n",
+                     restarts, rM, (long long)total);
       if (!std::isfinite(rM)) {
         set_error("non-finite residual in FP32-inner MINRES");
         return MBL_ERR_NUMERIC;
@@ -748,6 +754,9 @@ mbl_status minres_run(mbl_basis_s* b, const double* h_host, double sigma, const 
       mbl_status s2 = minres_core<float>(b, F, ws->r64, 1.0 / rM, (float*)ws->e, true, inner_tol,
                                          kmax - total, precond, ws, &it, &phi, s);
       if (s2 < 0) return s2;
+      if (verbose)
+        std::fprintf(stderr, "[mbl]   inner FP32 solve: %lld iterations, phi %.3e (target %.1e)\n",
+                     (long long)it, phi, inner_tol);
       total += it;
       hipLaunchKernelGGL(k_add_scaled_f32, dim3(flat_grid(n)), dim3(kWG), 0, s, n, rM,
                          (const float*)ws->e, x);
@@ -762,6 +771,9 @@ mbl_status minres_run(mbl_basis_s* b, const double* h_host, double sigma, const 
       mbl_status s3 = minres_core<double>(b, F, ws->r64, 1.0, e64, true, tol, kmax - total,
                                           precond, ws, &it, &phi, s);
       if (s3 < 0) return s3;
+      if (verbose)
+        std::fprintf(stderr, "[mbl]   FP64 finish: %lld iterations, phi %.3e, status %d\n",
+                     (long long)it, phi, (int)s3);
       total += it;
       MBL_HIP(launch_axpby(n, 1.0, e64, 1.0, x, s));
       int np = 0;
@@ -769,6 +781,8 @@ mbl_status minres_run(mbl_basis_s* b, const double* h_host, double sigma, const 
       double sums[2];
       MBL_TRY(reduce_to_host(ws, ws->partials1, np, 2, 2, sums, s));
       rM = std::sqrt(sums[0]);
+      if (verbose)
+        std::fprintf(stderr, "[mbl]   after the FP64 finish: ||r||_M^-1 = %.3e\n", rM);
     }
     inf.iters = total;
     inf.restarts = restarts;
