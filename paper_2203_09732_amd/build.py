@@ -3,7 +3,10 @@
     python paper_2203_09732_amd/build.py        (or build() from Python)
 
 Each .hip translation unit under csrc/ is compiled in parallel and linked
-into paper_2203_09732_amd/libmbl.so. It always recompiles.
+into paper_2203_09732_amd/libmbl.so; then the C example program
+(examples/mbl_example.c, a plain C99 caller of the C ABI) is compiled with
+the host C compiler into paper_2203_09732_amd/mbl_example. It always
+recompiles.
 """
 from __future__ import annotations
 
@@ -16,6 +19,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmbl.so")
+EXAMPLE = os.path.join(HERE, "mbl_example")
+CC = os.environ.get("CC", "gcc")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 BUILD = os.path.join(ROOT, "_build")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -49,8 +55,16 @@ def build(verbose: bool = False) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
     os.replace(tmp, OUT)
+    cmd = [CC, "-std=c99", "-O2", "-Wall", "-D__HIP_PLATFORM_AMD__",
+           "-I", os.path.join(ROOT, "include"), "-I", os.path.join(ROCM, "include"),
+           os.path.join(HERE, "examples", "mbl_example.c"), "-o", EXAMPLE,
+           "-L", HERE, "-lmbl", "-L", os.path.join(ROCM, "lib"), "-lamdhip64", "-lm",
+           "-Wl,-rpath,$ORIGIN", "-Wl,-rpath," + os.path.join(ROCM, "lib")]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"C example build failed:\n{r.stderr}")
     if verbose:
-        print("built", OUT)
+        print("built", OUT, "and", EXAMPLE)
     return OUT
 
 
