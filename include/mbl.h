@@ -122,9 +122,11 @@ mbl_status mbl_precond_apply(mbl_basis b, const double* h_host, double sigma, in
  * kmax iterations (MBL_WARN_NOCONV). With MBL_FP32_INNER the solve runs in
  * cycles: an FP32 MINRES solve of A e = r / ||r|| to a relative 1e-3 (smaller
  * near the end), x += ||r|| e in FP64, r = b - A x recomputed in FP64. A cycle
- * that fails to cut ||r||_{M^{-1}} tenfold (FP32 rounding limits a cycle to
- * about u_32 times the condition number), or the 60th cycle, ends the FP32
- * phase and FP64 MINRES finishes on the current residual. The stop test is
+ * that fails to cut ||r||_{M^{-1}} tenfold (the FP32 recurrence drifts from
+ * the true residual by roughly u_32 times the squared condition number, so
+ * near the middle of a large spectrum a cycle can stop having achieved
+ * nothing), or the 60th cycle, ends the FP32 phase and FP64 MINRES finishes
+ * on the current residual. The stop test is
  * then the FP64 ||r||_{M^{-1}} < tol. Synchronizes stream. info may be NULL. */
 typedef struct {
   int64_t iters;       /* MINRES iterations, summed over restarts */

@@ -714,10 +714,12 @@ mbl_status minres_run(mbl_basis_s* b, const double* h_host, double sigma, const 
   } else {
     // FP32 inner solves, FP64 residual recomputation and restart. Each cycle
     // solves A e = r / ||r||_{M^-1} in FP32 to a relative tolerance eta and
-    // updates x += ||r||_{M^-1} e in FP64. FP32 arithmetic bounds what one
-    // cycle can achieve (about u_32 times the condition number), so a cycle
-    // that does not cut the FP64 residual by kMinCycleGain ends the FP32
-    // phase and the solve is finished by FP64 MINRES on the same residual.
+    // updates x += ||r||_{M^-1} e in FP64. The FP32 recurrence drifts from
+    // the true residual by roughly u_32 times the squared condition number,
+    // so a cycle can report its tolerance without having reduced the true
+    // residual; a cycle that does not cut the FP64 residual by kMinCycleGain
+    // ends the FP32 phase and the solve is finished by FP64 MINRES on the
+    // same residual.
     const double eta = 1e-3;
     const double kMinCycleGain = 10.0;
     const int max_restarts = 60;
