@@ -368,6 +368,19 @@ def main():
     value = achieved
 
     progress(f"batched apply: {achieved:.1f} GB/s ({avg_launch * 1e6:.1f} us per launch)")
+    # attainable rate on this machine: a plain device copy of the same algorithmic
+    # bytes (read 8nR, write 8nR), rotated over the same buffers
+    ncopy = max(10, args.steps // 5)
+    for i in range(NPAIRS):
+        YS[i].copy_(XS[i])
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for k in range(ncopy):
+        YS[k % NPAIRS].copy_(XS[k % NPAIRS])
+    e1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = bytes_per_launch / (e0.elapsed_time(e1) * 1e-3 / ncopy) / 1e9
+    progress(f"device copy of the same bytes: {copy_gbs:.1f} GB/s")
     # the same products one realization per launch (single-realization kernel)
     xs = [X[:, r].contiguous() for r in range(R)]
     ys = [torch.empty_like(xs[0]) for _ in range(R)]
@@ -444,11 +457,17 @@ def main():
                      "traffic": measured_traffic(f"k_bapply<double,0,false,{L},{basis.lo_bits}>"),
                      "kernel": f"k_bapply<double,0,false,{L},{basis.lo_bits}>",
                      "bytes_per_launch": bytes_per_launch, "avg_launch_us": round(avg_launch * 1e6, 3)},
+        "attainable": {"copy_GBps": round(copy_gbs, 1),
+                       "frac_of_copy": round(achieved / copy_gbs, 4)},
         "apply_single_realization": {"GBps": round(16.0 * n / single_s / 1e9, 1),
                                      "avg_launch_us": round(single_s * 1e6, 3)},
         "minres_L22": minres,
         "wall_s": round(wall, 3),
     }
+    tr = out["roofline"]["traffic"]
+    if tr:
+        out["roofline"]["traffic_GBps"] = round(tr / avg_launch / 1e9, 1)
+        out["roofline"]["amplification"] = round(tr / bytes_per_launch, 3)
     if not args.no_eig:
         out["sec_per_eigenpair"] = eig_leg(mbl, torch, args.eig_L, args.eig_nev, args.eig_R,
                                            args.eig_batched_mixed)
