@@ -201,6 +201,11 @@ mbl_status mbl_eig_residual(mbl_basis b, const double* h_host, const double* E_h
  * MBL_ERR_NUMERIC for a zero or non-finite vector. */
 mbl_status mbl_entanglement_entropy(mbl_basis b, const double* psi_dev, int64_t ld, int nvec,
                                     int la, double* S_host, void* stream);
+/* The same for nvec x R vectors stored interleaved, element i of vector t of
+ * realization r at psi_dev[(t * n + i) * R + r] (the layout of
+ * mbl_si_lanczos_batched's eigenvectors). S_host[r * nvec + t]. */
+mbl_status mbl_entanglement_entropy_interleaved(mbl_basis b, const double* psi_dev, int R,
+                                                int nvec, int la, double* S_host, void* stream);
 
 /* ---- level-spacing ratio (Sec. IV): over the ascending sort of
  * evals_host[count] (count >= 3), r_k = min(d_k, d_{k-1}) / max(d_k, d_{k-1})

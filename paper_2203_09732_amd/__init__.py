@@ -80,6 +80,7 @@ _sig("mbl_si_lanczos", _i32, [_vp, _dp, _d, C.c_int, C.c_int, _d, _i64, _d, _d, 
 _sig("mbl_twist_expect", _i32, [_vp, _vp, _i64, C.c_int, _dp, _vp])
 _sig("mbl_entanglement_entropy", _i32, [_vp, _vp, _i64, C.c_int, C.c_int, _dp, _vp])
 _sig("mbl_spacing_ratio", _i32, [C.c_int, _dp, _dp, _dp])
+_sig("mbl_entanglement_entropy_interleaved", _i32, [_vp, _vp, C.c_int, C.c_int, C.c_int, _dp, _vp])
 _sig("mbl_eig_residual", _i32, [_vp, _dp, _dp, _vp, _i64, C.c_int, _dp, _vp])
 _sig("mbl_sigma_midpoint", _i32, [_vp, _dp, _d, C.c_int, _dp, _dp, _dp, _vp])
 _sig("mbl_dot", _i32, [_i64, _vp, _vp, _dp, _vp])
@@ -321,6 +322,26 @@ def entanglement_entropy(basis: Basis, psi, la: int | None = None, stream=None) 
                                         S.ctypes.data_as(_dp), _stream(stream)),
            "mbl_entanglement_entropy")
     return S
+
+
+def entanglement_entropy_batched(basis: Basis, U, la: int | None = None, stream=None):
+    """S[r, t] for the (nev, n, R) interleaved eigenvector blocks of
+    si_lanczos_batched (A = sites 1..la, default L/2)."""
+    import torch
+    if U.dim() == 2:
+        U = U[None]
+    _need_cuda(U, torch.float64, None, "U")
+    if not U.is_contiguous():
+        raise ValueError("U must be contiguous (nev, n, R)")
+    nvec, n, R = U.shape
+    if n != basis.n:
+        raise ValueError("U must be (nev, n, R) with n the basis dimension")
+    S = np.zeros(R * nvec)
+    la = basis.L // 2 if la is None else int(la)
+    _check(lib.mbl_entanglement_entropy_interleaved(basis.handle, _ptr(U), R, nvec, la,
+                                                    S.ctypes.data_as(_dp), _stream(stream)),
+           "mbl_entanglement_entropy_interleaved")
+    return S.reshape(R, nvec)
 
 
 def spacing_ratio(evals):

@@ -47,8 +47,8 @@ mbl_status eig_residual_run(mbl_basis_s* b, mbl_workspace_s* ws, const double* h
                             const double* E, const double* psi, int64_t ld, int nvec,
                             double* resid, hipStream_t s);
 // declared in schmidt.hip
-mbl_status entropy_run(mbl_basis_s* b, const double* psi, int64_t ld, int nvec, int la,
-                       double* S, hipStream_t s);
+mbl_status entropy_run(mbl_basis_s* b, const double* psi, int64_t ld, int64_t rstride, int R,
+                       int nvec, int la, double* S, hipStream_t s);
 mbl_status spacing_ratio_run(int count, const double* E, double* r, double* r_mean);
 
 static uint64_t binom(int n, int k) {
@@ -489,7 +489,21 @@ mbl_status mbl_entanglement_entropy(mbl_basis b, const double* psi_dev, int64_t 
   MBL_ARG(b && psi_dev && S_host, "NULL argument");
   MBL_ARG(nvec >= 1 && ld >= b->n, "need nvec >= 1 and ld >= n");
   MBL_ARG(la >= 1 && la <= b->L - 1, "need 1 <= la <= L - 1");
-  return entropy_run(b, psi_dev, ld, nvec, la, S_host, S(stream));
+  return entropy_run(b, psi_dev, ld, 1, 1, nvec, la, S_host, S(stream));
+}
+
+mbl_status mbl_entanglement_entropy_interleaved(mbl_basis b, const double* psi_dev, int R,
+                                                int nvec, int la, double* S_host, void* stream) {
+  clear_error();
+  MBL_ARG(b && psi_dev && S_host, "NULL argument");
+  MBL_ARG(R >= 1 && nvec >= 1, "need R >= 1 and nvec >= 1");
+  MBL_ARG((int64_t)R * nvec <= (int64_t)1 << 30, "R * nvec too large");
+  MBL_ARG(la >= 1 && la <= b->L - 1, "need 1 <= la <= L - 1");
+  std::vector<double> Sv((size_t)R * nvec);
+  MBL_TRY(entropy_run(b, psi_dev, b->n * (int64_t)R, R, R, R * nvec, la, Sv.data(), S(stream)));
+  for (int t = 0; t < nvec; ++t)
+    for (int r = 0; r < R; ++r) S_host[(size_t)r * nvec + t] = Sv[(size_t)t * R + r];
+  return MBL_OK;
 }
 
 mbl_status mbl_spacing_ratio(int count, const double* evals_host, double* r_host,

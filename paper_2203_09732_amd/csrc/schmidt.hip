@@ -64,9 +64,13 @@ __device__ __forceinline__ uint32_t cns_rank(uint32_t bits) {
   return r;
 }
 
+// vector v = t R + r of the input (t < nvec, r < R) has its element i at
+// psi[t ld + i rstride + r]: ld = n, rstride = R = 1 for column-major
+// vectors, ld = n R, rstride = R for R interleaved realizations
 __global__ __launch_bounds__(kWG) void k_schmidt_scatter(DevBasis B, SchmidtArgs A,
                                                          const double* __restrict__ psi,
-                                                         int64_t ld, int nvec,
+                                                         int64_t ld, int64_t rstride, int R,
+                                                         int64_t v0, int nv,
                                                          double* __restrict__ X) {
   extern __shared__ __align__(16) unsigned char smem[];
   FieldArgs F{};
@@ -78,7 +82,10 @@ __global__ __launch_bounds__(kWG) void k_schmidt_scatter(DevBasis B, SchmidtArgs
     const int k = __popc(sa);
     const int64_t ia = cns_rank(sa), ib = cns_rank(sb);
     const int64_t dst = A.xoff[k] + (A.a_rows[k] ? ib * A.m[k] + ia : ia * A.m[k] + ib);
-    for (int v = 0; v < nvec; ++v) X[(size_t)v * A.n + dst] = psi[(size_t)v * ld + row];
+    for (int j = 0; j < nv; ++j) {
+      const int64_t v = v0 + j, t = v / R, r = v % R;
+      X[(size_t)j * A.n + dst] = psi[(size_t)t * ld + (size_t)row * rstride + r];
+    }
   });
 }
 
@@ -193,8 +200,8 @@ static uint64_t hbinom(int n, int k) {
   return r;
 }
 
-mbl_status entropy_run(mbl_basis_s* b, const double* psi, int64_t ld, int nvec, int la,
-                       double* S, hipStream_t s) {
+mbl_status entropy_run(mbl_basis_s* b, const double* psi, int64_t ld, int64_t rstride, int R,
+                       int nvec, int la, double* S, hipStream_t s) {
   const int L = b->L, half = b->half;
   SchmidtArgs A{};
   A.la = la;
@@ -249,7 +256,7 @@ mbl_status entropy_run(mbl_basis_s* b, const double* psi, int64_t ld, int nvec, 
   for (int v0 = 0; v0 < nvec && st == MBL_OK; v0 += chunk) {
     const int nv = std::min(chunk, nvec - v0);
     hipLaunchKernelGGL(k_schmidt_scatter, dim3(row_grid(b)), dim3(kWG), row_lds_bytes(b), s,
-                       b->dev(), A, psi + (size_t)v0 * ld, ld, nv, X);
+                       b->dev(), A, psi, ld, rstride, R, (int64_t)v0, nv, X);
     const int ntiles = (int)tiles.size();
     hipLaunchKernelGGL(k_schmidt_gram, dim3((ntiles + 3) / 4, nv), dim3(kWG), 0, s, A, td,
                        ntiles, X, Gd);

@@ -120,6 +120,7 @@ def disorder_scan(Ls, hs, R=32, nev=20, first_seed=0):
             res = mbl.si_lanczos_batched(b, bt, fields, sig, nev, mmax=mmax, escale=esc,
                                          seed=first_seed)
             z = mbl.twist_expect_batched(b, bt, res.evecs)
+            S_all = mbl.entanglement_entropy_batched(b, res.evecs)     # (R, nev), la = L/2
             rr, ss, zz = [], [], []
             for r in range(R):
                 # the converged pairs (explicit residual within eig_tol * escale)
@@ -127,8 +128,7 @@ def disorder_scan(Ls, hs, R=32, nev=20, first_seed=0):
                 k = len(idx)
                 rr.append(mbl.spacing_ratio(res.evals[r][idx])[0] if k >= 3 else float("nan"))
                 if k:
-                    U = res.evecs[torch.as_tensor(idx, device=res.evecs.device), :, r].t()
-                    ss.append(float(np.mean(mbl.entanglement_entropy(b, U))))
+                    ss.append(float(np.mean(S_all[r][idx])))
                     zz.append(float(np.mean(np.abs(z[r][idx]) ** 2)))
                 else:
                     ss.append(float("nan"))
