@@ -229,9 +229,10 @@ mbl_status entropy_run(mbl_basis_s* b, const double* psi, int64_t ld, int64_t rs
     return MBL_ERR_ARG;
   }
   A.gtot = go;
-  // vectors per device pass: X and G of every vector of the pass in HBM
+  // vectors per device pass: X and G of every vector of the pass in HBM (at
+  // most 4 GiB), and at most 64 (the Gram launch's y dimension, host copies)
   const int chunk = (int)std::max<int64_t>(
-      1, std::min<int64_t>(nvec, ((int64_t)4 << 30) / (8 * (b->n + go))));
+      1, std::min<int64_t>({(int64_t)nvec, (int64_t)64, ((int64_t)4 << 30) / (8 * (b->n + go))}));
   double *X = nullptr, *Gd = nullptr;
   uint4* td = nullptr;
   auto release = [&] {
@@ -251,8 +252,11 @@ mbl_status entropy_run(mbl_basis_s* b, const double* psi, int64_t ld, int64_t rs
   std::vector<double> Gh((size_t)chunk * go);
   const int nthreads = (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
   if (hipMemcpy(td, tiles.data(), sizeof(uint4) * tiles.size(), hipMemcpyHostToDevice) !=
-      hipSuccess)
+      hipSuccess) {
+    (void)hipGetLastError();
+    set_error("copy of the Gram tile table failed");
     st = MBL_ERR_HIP;
+  }
   for (int v0 = 0; v0 < nvec && st == MBL_OK; v0 += chunk) {
     const int nv = std::min(chunk, nvec - v0);
     hipLaunchKernelGGL(k_schmidt_scatter, dim3(row_grid(b)), dim3(kWG), row_lds_bytes(b), s,
