@@ -207,6 +207,14 @@ mbl_status mbl_entanglement_entropy(mbl_basis b, const double* psi_dev, int64_t 
 mbl_status mbl_entanglement_entropy_interleaved(mbl_basis b, const double* psi_dev, int R,
                                                 int nvec, int la, double* S_host, void* stream);
 
+/* Host-only: eigenvalues of the m x m symmetric matrix a_host (row-major, all
+ * m^2 entries read; 1 <= m <= 20000), ascending, into w_host[m]: Householder
+ * reduction to tridiagonal form with scaled reflectors, columns below 1e-20
+ * max|a| taken as zero, then implicit QL on the reversed tridiagonal. This is
+ * the routine mbl_entanglement_entropy applies to its Schmidt blocks. Uses no
+ * device. MBL_ERR_NUMERIC if an eigenvalue needs more than 60 iterations. */
+mbl_status mbl_symmetric_eigenvalues(int m, const double* a_host, double* w_host);
+
 /* ---- level-spacing ratio (Sec. IV): over the ascending sort of
  * evals_host[count] (count >= 3), r_k = min(d_k, d_{k-1}) / max(d_k, d_{k-1})
  * with d_k = E_{k+1} - E_k. r_host[count-2] (may be NULL) receives r_1 ..

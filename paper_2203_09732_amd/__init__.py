@@ -80,6 +80,7 @@ _sig("mbl_si_lanczos", _i32, [_vp, _dp, _d, C.c_int, C.c_int, _d, _i64, _d, _d, 
 _sig("mbl_twist_expect", _i32, [_vp, _vp, _i64, C.c_int, _dp, _vp])
 _sig("mbl_entanglement_entropy", _i32, [_vp, _vp, _i64, C.c_int, C.c_int, _dp, _vp])
 _sig("mbl_spacing_ratio", _i32, [C.c_int, _dp, _dp, _dp])
+_sig("mbl_symmetric_eigenvalues", _i32, [C.c_int, _dp, _dp])
 _sig("mbl_entanglement_entropy_interleaved", _i32, [_vp, _vp, C.c_int, C.c_int, C.c_int, _dp, _vp])
 _sig("mbl_eig_residual", _i32, [_vp, _dp, _dp, _vp, _i64, C.c_int, _dp, _vp])
 _sig("mbl_sigma_midpoint", _i32, [_vp, _dp, _d, C.c_int, _dp, _dp, _dp, _vp])
@@ -342,6 +343,18 @@ def entanglement_entropy_batched(basis: Basis, U, la: int | None = None, stream=
                                                     S.ctypes.data_as(_dp), _stream(stream)),
            "mbl_entanglement_entropy_interleaved")
     return S.reshape(R, nvec)
+
+
+def symmetric_eigenvalues(A) -> np.ndarray:
+    """Ascending eigenvalues of a symmetric matrix, by the host routine the
+    entanglement entropy uses for its Schmidt blocks."""
+    A, Ap = _f64(A)
+    m = A.shape[0]
+    if A.ndim != 2 or A.shape != (m, m):
+        raise ValueError("A must be square")
+    w = np.zeros(m)
+    _check(lib.mbl_symmetric_eigenvalues(m, Ap, w.ctypes.data_as(_dp)), "mbl_symmetric_eigenvalues")
+    return w
 
 
 def spacing_ratio(evals):

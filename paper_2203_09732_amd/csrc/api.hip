@@ -50,6 +50,7 @@ mbl_status eig_residual_run(mbl_basis_s* b, mbl_workspace_s* ws, const double* h
 mbl_status entropy_run(mbl_basis_s* b, const double* psi, int64_t ld, int64_t rstride, int R,
                        int nvec, int la, double* S, hipStream_t s);
 mbl_status spacing_ratio_run(int count, const double* E, double* r, double* r_mean);
+mbl_status symmetric_eigenvalues_run(int m, const double* A, double* w);
 
 static uint64_t binom(int n, int k) {
   if (k < 0 || k > n) return 0;
@@ -504,6 +505,14 @@ mbl_status mbl_entanglement_entropy_interleaved(mbl_basis b, const double* psi_d
   for (int t = 0; t < nvec; ++t)
     for (int r = 0; r < R; ++r) S_host[(size_t)r * nvec + t] = Sv[(size_t)t * R + r];
   return MBL_OK;
+}
+
+mbl_status mbl_symmetric_eigenvalues(int m, const double* a_host, double* w_host) {
+  clear_error();
+  MBL_ARG(a_host && w_host, "NULL argument");
+  MBL_ARG(m >= 1 && m <= 20000, "need 1 <= m <= 20000");
+  for (size_t i = 0; i < (size_t)m * m; ++i) MBL_ARG(std::isfinite(a_host[i]), "non-finite entry");
+  return symmetric_eigenvalues_run(m, a_host, w_host);
 }
 
 mbl_status mbl_spacing_ratio(int count, const double* evals_host, double* r_host,

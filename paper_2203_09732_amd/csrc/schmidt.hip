@@ -329,6 +329,16 @@ mbl_status entropy_run(mbl_basis_s* b, const double* psi, int64_t ld, int64_t rs
   return st;
 }
 
+mbl_status symmetric_eigenvalues_run(int m, const double* A, double* w) {
+  std::vector<double> M(A, A + (size_t)m * m), ev;
+  if (sym_eigenvalues(m, M, ev) != 0) {
+    set_error("symmetric eigenvalues did not converge");
+    return MBL_ERR_NUMERIC;
+  }
+  std::copy(ev.begin(), ev.end(), w);
+  return MBL_OK;
+}
+
 mbl_status spacing_ratio_run(int count, const double* E, double* r, double* r_mean) {
   std::vector<double> e(E, E + count);
   std::sort(e.begin(), e.end());

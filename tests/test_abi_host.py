@@ -120,3 +120,43 @@ def test_spacing_ratio_rejects_bad_input(mbl):
     for E in ([1.0, 2.0], [0.0, np.nan, 1.0, 2.0], [0.0, np.inf, 1.0]):
         with pytest.raises(mbl.MblError):
             mbl.spacing_ratio(E)
+
+
+def _graded_psd(rng, m, c, r, decay, zero_row):
+    U, _ = np.linalg.qr(rng.standard_normal((m, m)))
+    V, _ = np.linalg.qr(rng.standard_normal((c, c)))
+    s = np.zeros(m)
+    s[:r] = decay ** np.arange(r)
+    X = (U * s) @ V[:m, :]
+    if zero_row is not None:
+        X[zero_row, :] = 0.0
+    return X @ X.T
+
+
+def test_symmetric_eigenvalues_graded_and_rank_deficient(mbl):
+    """The host routine behind the entanglement entropy, on the matrices its
+    Schmidt blocks produce: Gram matrices of rank r <= m with singular values
+    decaying geometrically, zero rows, rank one (all entries equal), and a
+    column far below the trailing block. Against LAPACK, to 2e-14 ||A||."""
+    rng = np.random.default_rng(7)
+    cases = []
+    for t in range(150):
+        m = int(rng.integers(1, 90))
+        c = int(rng.integers(m, 2 * m + 5))
+        r = int(rng.integers(1, m + 1))
+        cases.append(_graded_psd(rng, m, c, r, 10.0 ** (-rng.uniform(0, 3)),
+                                 int(rng.integers(0, m)) if t % 7 == 0 else None))
+    cases.append(np.full((70, 70), 437.5))
+    B = rng.standard_normal((12, 12))
+    B = B @ B.T
+    B[1:, 0] = B[0, 1:] = 1e-160 * rng.standard_normal(11)
+    cases.append(B)
+    for A in cases:
+        w = mbl.symmetric_eigenvalues(A)
+        ref = np.linalg.eigvalsh(A)
+        assert np.abs(w - ref).max() <= 2e-14 * max(np.abs(ref).max(), 1e-300)
+
+
+def test_symmetric_eigenvalues_rejects_bad_input(mbl):
+    with pytest.raises(mbl.MblError):
+        mbl.symmetric_eigenvalues(np.array([[1.0, np.nan], [np.nan, 1.0]]))
