@@ -161,6 +161,14 @@ def eig_leg(mbl, torch, L, nev, R, batched_mixed=False):
             out["adjoint_fp64"] = {"value": round(dt / max(res.nconv, 1), 4),
                                    "unit": "s per eigenpair (all L derivatives of E and |z|^2)",
                                    "minres_iters_per_pair": its // max(res.nconv, 1)}
+            # eigenstate observables of the same pairs: half-chain entropy, spacing ratio
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            S = mbl.entanglement_entropy(b, res.evecs)
+            dt = time.perf_counter() - t
+            out["observables_fp64"] = {"S_half_chain_mean": round(float(np.mean(S)), 6),
+                                       "entropy_ms_per_vector": round(dt / len(S) * 1e3, 3),
+                                       "r_mean": round(mbl.spacing_ratio(res.evals)[0], 6)}
         if prec != "fp64" and not batched_mixed:
             continue
         bb = mbl.Basis(L, tune.best_lo_bits(L, R, "fp64" if prec == "fp64" else "fp32"))
