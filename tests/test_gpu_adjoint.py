@@ -149,12 +149,3 @@ def test_eig_grad_fd_by_inverse_iteration_L18(gpu, torch):
     eE, ez = _fd_subset(gpu, torch, 18, seeds=(0,), sites=(0, 7, 12))
     assert eE <= 2e-5
     assert ez <= 1e-3
-
-
-@pytest.mark.skipif(not __import__("os").environ.get("MBL_LONG_TESTS"),
-                    reason="L=20 subset (3 sites x 2 seeds) takes several minutes; set MBL_LONG_TESTS=1")
-def test_eig_grad_fd_by_inverse_iteration_L20(gpu, torch):
-    say("eig_grad vs FD by inverse iteration, L=20, 3 sites x 2 seeds")
-    eE, ez = _fd_subset(gpu, torch, 20, seeds=(0, 1), sites=(0, 9, 16))
-    assert eE <= 2e-5
-    assert ez <= 1e-3
