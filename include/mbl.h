@@ -195,7 +195,7 @@ mbl_status mbl_eig_residual(mbl_basis b, const double* h_host, const double* E_h
  * A; the coefficients of each block are gathered on the device and their
  * Gram matrices (min(C(la,k), C(L-la,L/2-k)) squared) formed on the FP64
  * matrix cores; the eigenvalues of the blocks are found on the host
- * (Householder tridiagonalisation, implicit QL) with up to 16 threads.
+ * (Householder tridiagonalisation, symmetric QR) with up to 16 threads.
  * S_host[nvec]. Allocates device scratch of at most 4 GiB (16 n bytes per
  * vector of a pass) and frees it before returning. Synchronizes stream.
  * MBL_ERR_NUMERIC for a zero or non-finite vector. */
@@ -210,9 +210,10 @@ mbl_status mbl_entanglement_entropy_interleaved(mbl_basis b, const double* psi_d
 /* Host-only: eigenvalues of the m x m symmetric matrix a_host (row-major, all
  * m^2 entries read; 1 <= m <= 20000), ascending, into w_host[m]: Householder
  * reduction to tridiagonal form with scaled reflectors, columns below 1e-20
- * max|a| taken as zero, then implicit QL on the reversed tridiagonal. This is
- * the routine mbl_entanglement_entropy applies to its Schmidt blocks. Uses no
- * device. MBL_ERR_NUMERIC if an eigenvalue needs more than 60 iterations. */
+ * max|a| taken as zero, then the symmetric QR iteration of mbl_tridiag_eig.
+ * This is the routine mbl_entanglement_entropy applies to its Schmidt blocks.
+ * Uses no device. MBL_ERR_NUMERIC if an eigenvalue needs more than 60 QR
+ * steps. */
 mbl_status mbl_symmetric_eigenvalues(int m, const double* a_host, double* w_host);
 
 /* ---- level-spacing ratio (Sec. IV): over the ascending sort of
@@ -312,10 +313,11 @@ mbl_status mbl_dot(int64_t n, const double* x_dev, const double* y_dev, double* 
                    void* stream);
 
 /* Host-only: eigen-decomposition of the k x k symmetric tridiagonal T_k of
- * Alg. 1 (diagonal alpha[k], off-diagonal beta[k-1]) by implicit QL
- * iterations. evals_host[k] ascending; evecs_host k x k column-major, column i
+ * Alg. 1 (diagonal alpha[k], off-diagonal beta[k-1]) by the symmetric QR
+ * algorithm (implicit steps with Wilkinson shift, Golub & Van Loan Sec. 8.3).
+ * evals_host[k] ascending; evecs_host k x k column-major, column i
  * for evals_host[i]. Uses no device. MBL_ERR_NUMERIC if an eigenvalue needs
- * more than 60 iterations. */
+ * more than 60 QR steps. */
 mbl_status mbl_tridiag_eig(int k, const double* alpha_host, const double* beta_host,
                            double* evals_host, double* evecs_host);
 

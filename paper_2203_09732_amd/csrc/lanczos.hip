@@ -110,67 +110,77 @@ static int lgrid(int64_t n) {
 }
 
 // ---------------------------------------------------------------------------
-// host symmetric tridiagonal eigensolver: implicit QL iterations with the
-// Wilkinson-type shift from the leading 2 x 2 block, accumulating the
-// rotations into the eigenvector matrix (Golub & Van Loan, Sec. 8.3).
-// alpha[0..k-1] diagonal, beta[0..k-2] off-diagonal. evals ascending,
-// evecs k x k column-major (column i belongs to evals[i]); with evecs NULL
-// only the eigenvalues are formed. Returns 0 on success, -1 if an eigenvalue
-// needed more than 60 iterations.
+// host symmetric tridiagonal eigensolver: the symmetric QR algorithm of
+// Golub & Van Loan (Matrix Computations, Sec. 8.3, the implicit symmetric QR
+// step with Wilkinson shift, Alg. 8.3.2, inside the deflating driver of
+// Alg. 8.3.3). Off-diagonal entries below eps (|d_i| + |d_{i+1}|) are set to
+// zero; the trailing unreduced block [lo, hi] gets one implicit QR step: the
+// Wilkinson shift mu from its trailing 2 x 2 block, a Givens rotation in the
+// plane (lo, lo+1) chosen from the first column of T - mu I, and the bulge it
+// creates chased down to hi by further rotations. The rotations are
+// accumulated into the eigenvector matrix. alpha[0..k-1] diagonal,
+// beta[0..k-2] off-diagonal. evals ascending, evecs k x k column-major
+// (column i belongs to evals[i]); with evecs NULL only the eigenvalues are
+// formed. Returns 0 on success, -1 if a block needed more than 60 QR steps
+// per eigenvalue.
 int tridiag_eig(int k, const double* alpha, const double* beta, double* evals, double* evecs) {
   const bool vec = evecs != nullptr;
-  std::vector<double> d(alpha, alpha + k), e(k, 0.0), Z(vec ? (size_t)k * k : 0, 0.0);
+  const double eps = 2.220446049250313e-16;
+  std::vector<double> d(alpha, alpha + k), e(k > 1 ? k - 1 : 1, 0.0),
+      Z(vec ? (size_t)k * k : 0, 0.0);
   for (int i = 0; i + 1 < k; ++i) e[i] = beta[i];
   if (vec)
     for (int i = 0; i < k; ++i) Z[(size_t)i * k + i] = 1.0;
-  for (int l = 0; l < k; ++l) {
-    int iter = 0;
-    for (;;) {
-      int m = l;
-      for (; m + 1 < k; ++m) {
-        const double dd = std::fabs(d[m]) + std::fabs(d[m + 1]);
-        if (std::fabs(e[m]) <= 1e-300 || std::fabs(e[m]) <= 0.5 * 2.220446049250313e-16 * dd) break;
+  int hi = k - 1, steps = 0;
+  while (hi > 0) {
+    // deflation: negligible couplings become exact zeros
+    for (int i = 0; i < hi; ++i)
+      if (std::fabs(e[i]) <= eps * (std::fabs(d[i]) + std::fabs(d[i + 1])) ||
+          std::fabs(e[i]) <= 1e-300)
+        e[i] = 0.0;
+    while (hi > 0 && e[hi - 1] == 0.0) {   // d[hi] has converged
+      --hi;
+      steps = 0;
+    }
+    if (hi == 0) break;
+    int lo = hi - 1;
+    while (lo > 0 && e[lo - 1] != 0.0) --lo;
+    if (++steps > 60) return -1;
+    // Wilkinson shift: the eigenvalue of the trailing 2 x 2 block nearer d[hi]
+    const double half = 0.5 * (d[hi - 1] - d[hi]), bh = e[hi - 1];
+    const double root = std::hypot(half, bh);
+    const double mu = d[hi] - bh * (bh / (half + (half >= 0.0 ? root : -root)));
+    // the first rotation from the first column of T - mu I, then the bulge
+    // (x, z) = (T[j][j-1], T[j+1][j-1]) chased to the bottom of the block
+    double x = d[lo] - mu, z = e[lo];
+    for (int j = lo; j < hi; ++j) {
+      const double r = std::hypot(x, z);
+      double c = 1.0, s = 0.0;
+      if (r != 0.0) {
+        c = x / r;
+        s = z / r;
       }
-      if (m == l) break;
-      if (++iter > 60) return -1;
-      // shift from the 2 x 2 block at (l, l+1)
-      double g = (d[l + 1] - d[l]) / (2.0 * e[l]);
-      double r = std::hypot(g, 1.0);
-      g = d[m] - d[l] + e[l] / (g + (g >= 0 ? r : -r));
-      double s = 1.0, c = 1.0, p = 0.0;
-      int i = m - 1;
-      bool underflow = false;
-      for (; i >= l; --i) {
-        const double f = s * e[i];
-        const double b = c * e[i];
-        r = std::hypot(f, g);
-        e[i + 1] = r;
-        if (r == 0.0) {   // split: restart this l with the reduced block
-          d[i + 1] -= p;
-          e[m] = 0.0;
-          underflow = true;
-          break;
-        }
-        s = f / r;
-        c = g / r;
-        g = d[i + 1] - p;
-        r = (d[i] - g) * s + 2.0 * c * b;
-        p = s * r;
-        d[i + 1] = g + p;
-        g = c * r - b;
-        if (!vec) continue;
-        double* zi = &Z[(size_t)i * k];
-        double* zi1 = &Z[(size_t)(i + 1) * k];
+      if (j > lo) e[j - 1] = r;
+      // T <- G^T T G in the plane (j, j+1), G = [[c, -s], [s, c]]
+      const double a = d[j], bb = e[j], cc = d[j + 1];
+      const double cs = c * s;
+      d[j] = c * c * a + 2.0 * cs * bb + s * s * cc;
+      d[j + 1] = s * s * a - 2.0 * cs * bb + c * c * cc;
+      e[j] = cs * (cc - a) + (c * c - s * s) * bb;
+      if (j + 1 < hi) {
+        z = s * e[j + 1];      // the new bulge at (j + 2, j)
+        e[j + 1] *= c;
+        x = e[j];
+      }
+      if (vec) {
+        double* zj = &Z[(size_t)j * k];
+        double* zj1 = &Z[(size_t)(j + 1) * k];
         for (int row = 0; row < k; ++row) {
-          const double t = zi1[row];
-          zi1[row] = s * zi[row] + c * t;
-          zi[row] = c * zi[row] - s * t;
+          const double t0 = zj[row], t1 = zj1[row];
+          zj[row] = c * t0 + s * t1;
+          zj1[row] = c * t1 - s * t0;
         }
       }
-      if (underflow) continue;
-      d[l] -= p;
-      e[l] = g;
-      e[m] = 0.0;
     }
   }
   std::vector<int> order(k);

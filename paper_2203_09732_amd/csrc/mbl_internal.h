@@ -234,7 +234,7 @@ mbl_status minres_run(mbl_basis_s* b, const double* h_host, double sigma, const 
                       bool x0_zero, mbl_workspace_s* ws, mbl_minres_info* info, hipStream_t s,
                       const double* defl = nullptr, double theta = 0.0);
 
-// host symmetric tridiagonal eigensolver (implicit QL with shifts)
+// host symmetric tridiagonal eigensolver (symmetric QR with Wilkinson shifts)
 int tridiag_eig(int k, const double* alpha, const double* beta, double* evals, double* evecs);
 
 }  // namespace mbl

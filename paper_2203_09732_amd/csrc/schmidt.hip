@@ -17,7 +17,7 @@
 //   2. k_schmidt_gram forms G_k = X_k X_k^T on the FP64 matrix cores, one
 //      wavefront per 16 x 16 tile (v_mfma_f64_16x16x4f64).
 // On the host the eigenvalues of every G_k (Householder tridiagonalisation,
-// then implicit QL, eigenvalues only) are divided by Tr rho_A = sum_k tr G_k
+// then symmetric QR, eigenvalues only) are divided by Tr rho_A = sum_k tr G_k
 // and S = -sum p ln p; (vector, block) tasks run on up to 16 threads and
 // are combined in a fixed order.
 #include "rows.h"
@@ -128,13 +128,13 @@ __global__ __launch_bounds__(kWG) void k_schmidt_gram(SchmidtArgs A, const uint4
 // ---------------------------------------------------------------------------
 // host: eigenvalues of a symmetric matrix (row-major, overwritten) by
 // Householder reduction to tridiagonal form (Golub & Van Loan, Sec. 8.3.1),
-// then the implicit QL iterations of tridiag_eig without eigenvectors. A
+// then the symmetric QR iterations of tridiag_eig without eigenvectors. A
 // column whose entries are all below 1e-20 max|A| is taken as zero (the
 // eigenvalues move by less than that); otherwise a rank-deficient block is
 // reduced to a tridiagonal graded down into the subnormal range, where the
-// QL deflation test no longer works. The reduction leaves the large entries
-// at the top of the tridiagonal; it is handed to QL reversed (the same
-// eigenvalues), large entries last, the grading QL converges on.
+// deflation test no longer works. The reduction leaves the large entries at
+// the top of the tridiagonal and the small ones at the bottom, the grading
+// the QR iteration (shifted and deflated from the bottom) converges on.
 static int sym_eigenvalues(int m, std::vector<double>& A, std::vector<double>& w) {
   w.assign(m, 0.0);
   if (m == 1) {
@@ -188,8 +188,6 @@ static int sym_eigenvalues(int m, std::vector<double>& A, std::vector<double>& w
   e[m - 2] = A[(size_t)(m - 1) * m + (m - 2)];
   if (std::fabs(e[m - 2]) <= negligible) e[m - 2] = 0.0;
   d[m - 1] = A[(size_t)(m - 1) * m + (m - 1)];
-  std::reverse(d.begin(), d.end());
-  std::reverse(e.begin(), e.begin() + (m - 1));
   return tridiag_eig(m, d.data(), e.data(), w.data(), nullptr);
 }
 
