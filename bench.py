@@ -10,11 +10,16 @@ realization r of the batch (32 x 16n = 361 MB of algorithmic HBM traffic,
 more than the 256 MB last-level cache). ``value`` is the algorithmic
 apply_H bandwidth (16n bytes per product: read x once, write y once) of the
 whole step; the roofline object reports the same figure against the HBM
-peak. Time per MINRES iteration at L=22 (FP64 and FP32-inner) and, with
---eig, seconds per converged eigenpair at L=22 are reported beside it.
+peak. Time per MINRES iteration at L=22 (FP64 and FP32-inner) and seconds
+per converged eigenpair are reported beside it: measured at L=18 (the
+largest chain whose eigen-runs fit the bench's few minutes; one FP64 pair at
+L=22 takes about three minutes) in the single, batched and
+FP32-inner forms, and at L=14 (the plain 10-pair workload) for comparison
+with the oracle's dense solver on the host.
 
-The CPU baseline is the oracle's sparse matrix-vector product on the host
-cores over a bounded sample of the same workload.
+The CPU baseline is the oracle on the host cores over bounded samples: its
+sparse matrix-vector product at L=22 (the headline unit), and seconds per
+eigenpair of its dense eigensolver on the L=14 workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--eig] [--no-cpu]
 """
@@ -78,9 +83,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=500)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--realizations", type=int, default=32)
-    ap.add_argument("--eig-L", type=int, default=16, help="chain length of the eigenpair leg")
+    ap.add_argument("--eig-L", type=int, default=18, help="chain length of the eigenpair leg")
     ap.add_argument("--eig-nev", type=int, default=6)
-    ap.add_argument("--eig-R", type=int, default=16, help="realizations of the batched eigen leg")
+    ap.add_argument("--eig-R", type=int, default=8, help="realizations of the batched eigen leg")
     ap.add_argument("--no-eig", action="store_true", help="skip the eigenpair leg")
     ap.add_argument("--eig-batched-mixed", action="store_true",
                     help="also time the lockstep FP32-inner eigen leg (minutes)")
@@ -93,10 +98,37 @@ def parse():
     return ap.parse_args()
 
 
-def cpu_baseline(fields, sigmas, L, budget_s=15.0):
-    """Oracle CSR product on the host, bounded to about budget_s seconds."""
-    from oracle import model
-    nthreads = 1   # scipy's CSR matvec runs on one thread
+def host_info():
+    """Host cores, CPU model and the BLAS the oracle's dense solver runs on."""
+    info = {"nproc": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+            else os.cpu_count()}
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    info["cpu_model"] = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        import threadpoolctl
+        blas = [p for p in threadpoolctl.threadpool_info() if p.get("user_api") == "blas"]
+        if blas:
+            info["blas"] = f"{blas[0].get('internal_api')} {blas[0].get('version')}"
+            info["blas_threads"] = blas[0].get("num_threads")
+    except Exception:
+        pass
+    return info
+
+
+def cpu_baseline(fields, sigmas, L, budget_s=12.0):
+    """The oracle on the host over bounded samples: its CSR product (H - sigma) x
+    at the headline L (one thread: scipy's CSR product is serial), and seconds
+    per eigenpair of its dense eigensolver (LAPACK through the threaded BLAS)
+    on the L=14 workload (10 pairs nearest the spectral midpoint)."""
+    from oracle import lanczos, model
+    from workloads import WORKLOADS
+    nthreads = 1
     t_build = time.perf_counter()
     H = model.hamiltonian_csr(L, fields[0])
     t_build = time.perf_counter() - t_build
@@ -108,12 +140,28 @@ def cpu_baseline(fields, sigmas, L, budget_s=15.0):
         y = H @ x - sigmas[0] * x
         done += 1
     dt = time.perf_counter() - t0
-    del y
+    del y, H
+    info = host_info()
+    cfg = WORKLOADS["plain_L14"]
+    from workloads import disorder_fields
+    Hd = model.hamiltonian_dense(cfg["L"], disorder_fields(cfg["L"], cfg["h"], cfg["seeds"][0]))
+    t1 = time.perf_counter()
+    w = np.linalg.eigvalsh(Hd)
+    sigma14 = 0.5 * (w[0] + w[-1])
+    E, _V = lanczos.eigenpairs_dense(Hd, sigma14, cfg["nev"])
+    t_eig = time.perf_counter() - t1
     return {
         "value": round(16.0 * n * done / dt / 1e9, 3), "unit": "GB/s", "cores": nthreads,
         "kind": "oracle",
         "sample": f"{done} products (H - sigma) x of realization 0 at L={L} with the oracle's "
                   f"scipy CSR matrix (build {t_build:.1f} s excluded), {dt:.1f} s",
+        "host": info,
+        "sec_per_eigenpair_L14": {
+            "value": round(t_eig / cfg["nev"], 4), "unit": "s per eigenpair",
+            "threads": info.get("blas_threads"),
+            "sample": f"oracle dense eigensolver (eigvalsh for sigma, then eigh and the "
+                      f"{cfg['nev']} pairs nearest sigma) on the L={cfg['L']} h={cfg['h']} "
+                      f"seed {cfg['seeds'][0]} workload, n={Hd.shape[0]}, {t_eig:.1f} s"},
     }
 
 
@@ -124,14 +172,16 @@ def progress(msg):
 def eig_leg(mbl, torch, L, nev, R, batched_mixed=False):
     """Seconds per converged eigenpair (explicit FP64 residual <= 1e-10 escale)
     of the whole path (sigma, SI-Lanczos with MINRES, Ritz vectors, residual
-    checks, twist) on L, one realization per launch and R in lockstep, FP64 and
-    FP32-inner MINRES (the lockstep FP32-inner run only with batched_mixed: it
-    takes several times the FP64 run)."""
+    checks, twist) at chain length L: one realization per call in FP64 and
+    with FP32-inner MINRES, and R realizations in lockstep in FP64 (the
+    lockstep FP32-inner run only with batched_mixed). Every call is timed
+    whole, with sigma; nothing is projected."""
     from workloads import disorder_fields
     from paper_2203_09732_amd import tune
     h = 3.0
     fields = [disorder_fields(L, h, 5000 + r) for r in range(R)]
-    out = {"L": L, "nev": nev, "h": h, "eig_tol": 1e-10, "minres_tol": 1e-12}
+    out = {"L": L, "nev": nev, "h": h, "eig_tol": 1e-10, "minres_tol": 1e-12,
+           "seeds": f"5000..{5000 + R - 1}"}
     for prec in ("fp64", "fp32_inner"):
         b = mbl.Basis(L)
         torch.cuda.synchronize()
@@ -145,7 +195,8 @@ def eig_leg(mbl, torch, L, nev, R, batched_mixed=False):
         progress(f"eig leg L={L} single {prec}: {dt:.1f} s, {res.nconv} pairs")
         out["single_" + prec] = {"value": round(dt / max(res.nconv, 1), 4), "nconv": int(res.nconv),
                                  "realizations": 1, "seconds": round(dt, 3), "steps": int(res.steps),
-                                 "minres_iters": int(res.minres_iters)}
+                                 "minres_iters": int(res.minres_iters),
+                                 "max_rel_resid": float(res.max_rel_resid)}
         if prec == "fp64":
             # adjoint derivatives dE/dh and d|z|^2/dh of every converged pair
             torch.cuda.synchronize()
@@ -194,6 +245,28 @@ def eig_leg(mbl, torch, L, nev, R, batched_mixed=False):
                                   "minres_iters": int(resb.minres_iters)}
     out["unit"] = "s per converged eigenpair"
     return out
+
+
+def plain_leg(mbl, torch):
+    """The L=14 plain workload (h = 3, seed 0, the 10 pairs nearest the
+    spectral midpoint, FP64): seconds per converged eigenpair on the GPU, the
+    same unit as the oracle's dense solver in cpu_baseline."""
+    from workloads import WORKLOADS, disorder_fields
+    cfg = WORKLOADS["plain_L14"]
+    f = disorder_fields(cfg["L"], cfg["h"], cfg["seeds"][0])
+    b = mbl.Basis(cfg["L"])
+    mbl.si_lanczos(b, f, 0.0, 2, seed=1)   # first-call setup (graph capture) outside the timing
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    lo, hi, sg = mbl.sigma_midpoint(b, f, 1e-12)
+    res = mbl.si_lanczos(b, f, sg, cfg["nev"], escale=max(abs(lo), abs(hi)), seed=7)
+    mbl.twist_expect(b, res.evecs)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    progress(f"plain L=14 leg: {dt:.2f} s, {res.nconv} pairs")
+    return {"L": cfg["L"], "nev": cfg["nev"], "h": cfg["h"], "value": round(dt / max(res.nconv, 1), 4),
+            "unit": "s per converged eigenpair", "nconv": int(res.nconv), "seconds": round(dt, 3),
+            "steps": int(res.steps), "minres_iters": int(res.minres_iters)}
 
 
 def largest_leg(mbl, torch, steps=20):
@@ -277,26 +350,6 @@ def largest_leg(mbl, torch, steps=20):
     out["minres_batched_R16_fp64"] = {"iters": it, "us_per_iter": round(dt / it * 1e6, 1),
                                       "us_per_realization_iter": round(dt / it / R * 1e6, 2)}
     progress(f"largest L=26: minres batched R=16 {dt / it * 1e6:.1f} us/iter")
-    return out
-
-
-# MINRES iterations of one tol-1e-12 solve at L=22, h=3.5, sigma at the
-# midpoint (realization 0), measured on MI355X with minres_solve.
-L22_ITERS = {"fp64": 946392, "fp32_inner": 2102188}
-# shift-invert Lanczos steps for 20 pairs at eig_tol 1e-10 with exact solves
-# (oracle calibration at L=16); the count is nearly independent of L.
-L22_STEPS_20 = 47
-
-
-def l22_projection(minres):
-    """Seconds per eigenpair at L=22 (20 pairs) projected from the per-iteration
-    times measured in this run and the measured L=22 iteration counts."""
-    out = {"kind": "projection: live us/iteration x measured iterations per solve x steps / pairs",
-           "steps": L22_STEPS_20, "pairs": 20, "iters_per_solve": L22_ITERS}
-    for form, key in (("single_fp64", "fp64"), ("single_fp32_inner", "fp32_inner"),
-                      ("batched_fp64", "fp64"), ("batched_fp32_inner", "fp32_inner")):
-        us = minres[form]["us_per_realization_iter"]
-        out[form] = round(us * 1e-6 * L22_ITERS[key] * L22_STEPS_20 / 20, 1)
     return out
 
 
@@ -424,7 +477,11 @@ def main():
         progress(f"minres single {prec}: {dt / max(info.iters, 1) * 1e6:.1f} us/iter")
         minres["single_" + prec] = {"iters": int(info.iters),
                                     "us_per_iter": round(dt / max(info.iters, 1) * 1e6, 2),
-                                    "us_per_realization_iter": round(dt / max(info.iters, 1) * 1e6, 2)}
+                                    "us_per_realization_iter": round(dt / max(info.iters, 1) * 1e6, 2),
+                                    # ten n-vectors (z x 2, q x 3, d x 2, p, x, b): under the
+                                    # 256 MB last-level cache at L=22
+                                    "footprint_bytes": int(10 * n * (8 if prec == "fp64" else 4)),
+                                    "cache_resident": True}
     Bn = (X / X.norm(dim=0, keepdim=True)).contiguous()
     for prec in ("fp64", "fp32_inner"):
         mbl.minres_solve_batched(basis, batch, fields, sigmas, Bn, tol=1e-300,
@@ -439,7 +496,9 @@ def main():
         progress(f"minres batched {prec}: {dt / max(it, 1) * 1e6:.1f} us/iter")
         minres["batched_" + prec] = {"iters": it, "realizations": R,
                                      "us_per_iter": round(dt / max(it, 1) * 1e6, 2),
-                                     "us_per_realization_iter": round(dt / max(it, 1) / R * 1e6, 2)}
+                                     "us_per_realization_iter": round(dt / max(it, 1) / R * 1e6, 2),
+                                     "footprint_bytes": int(18 * n * R * (8 if prec == "fp64" else 4)),
+                                     "cache_resident": False}
 
     out = {
         "metric": "apply_H HBM GB/s + sec per converged eigenpair at L=22, FP64 vs mixed/batched",
@@ -468,7 +527,8 @@ def main():
         "attainable": {"copy_GBps": round(copy_gbs, 1),
                        "frac_of_copy": round(achieved / copy_gbs, 4)},
         "apply_single_realization": {"GBps": round(16.0 * n / single_s / 1e9, 1),
-                                     "avg_launch_us": round(single_s * 1e6, 3)},
+                                     "avg_launch_us": round(single_s * 1e6, 3),
+                                     "footprint_bytes": int(16 * n), "cache_resident": True},
         "minres_L22": minres,
         "wall_s": round(wall, 3),
     }
@@ -479,7 +539,7 @@ def main():
     if not args.no_eig:
         out["sec_per_eigenpair"] = eig_leg(mbl, torch, args.eig_L, args.eig_nev, args.eig_R,
                                            args.eig_batched_mixed)
-        out["sec_per_eigenpair_L22_projection"] = l22_projection(minres)
+        out["sec_per_eigenpair_plain_L14"] = plain_leg(mbl, torch)
     if args.largest:
         out["largest_L26"] = largest_leg(mbl, torch)
     if not args.no_cpu:

@@ -3,14 +3,17 @@
 * ``precond``: MINRES iterations and time to solve (H - sigma) x = b at the
   spectral midpoint with the identity, Jacobi and row-norm preconditioners
   (the comparison of Sec. II / Sec. IV A: iterations against L for h = 3, 4).
-* ``memory``: device bytes of a workspace against L, next to the linear model
-  8 n (13 + mmax + 1) and the paper's 8 n (9 + m) (Sec. IV A).
+* ``memory``: device memory a workspace takes against L, measured as the
+  drop of the device's free memory (hipMemGetInfo) across its creation, next
+  to the library's own count, the linear model 8 n (13 + mmax + 1) and the
+  paper's 8 n (9 + m) (Sec. IV A).
 * ``scan``: the disorder scan of Sec. IV: for each (L, h), R realizations
   solved together in the batched form (the nev pairs nearest each one's
   spectral midpoint), then per realization the mean level-spacing ratio,
   the mean half-chain entanglement entropy and the mean |z|^2 over its
   eigenstates; the row reports their mean and standard deviation over
-  realizations, next to the GOE and Poisson ratios and Eq. (ee_random).
+  realizations, next to the GOE and Poisson ratios and Eq. (ee_random), and
+  the per-realization values (with sigma and the eigenvalues).
 * ``eig``: one full shift-invert Lanczos run (sigma at the spectral midpoint,
   the nev pairs nearest it, MINRES tol 1e-12, eig_tol 1e-10), its time per
   converged eigenpair, steps and MINRES iterations (set MBL_VERBOSE=1 for a
@@ -59,11 +62,19 @@ def precond_iterations(Ls, hs, seeds, kinds=("id", "jacobi", "row"), tol=1e-12, 
 
 
 def memory_curve(Ls, mmax=130):
+    import torch
+
     import paper_2203_09732_amd as mbl
+    mbl.Workspace(mbl.Basis(8), 2)        # first allocations of the process outside the count
     for L in Ls:
         b = mbl.Basis(L)
+        torch.cuda.synchronize()
+        free0 = torch.cuda.mem_get_info()[0]
         ws = mbl.Workspace(b, mmax)
-        yield {"study": "memory", "L": L, "n": b.n, "mmax": mmax, "workspace_bytes": ws.bytes,
+        torch.cuda.synchronize()
+        free1 = torch.cuda.mem_get_info()[0]
+        yield {"study": "memory", "L": L, "n": b.n, "mmax": mmax,
+               "device_bytes_taken": int(free0 - free1), "workspace_bytes": ws.bytes,
                "model_8n(13+mmax+1)": 8 * b.n * (13 + mmax + 1),
                "paper_model_8n(9+m)": 8 * b.n * (9 + mmax)}
         del ws
@@ -135,6 +146,9 @@ def disorder_scan(Ls, hs, R=32, nev=20, first_seed=0):
                     zz.append(float("nan"))
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
+            per = [{"seed": first_seed + r, "sigma": float(sig[r]), "nconv": int(res.nconv[r]),
+                    "r": float(rr[r]), "S": float(ss[r]), "z2": float(zz[r]),
+                    "evals": [float(e) for e in res.evals[r]]} for r in range(R)]
             rr, ss, zz = np.array(rr), np.array(ss), np.array(zz)
             yield {"study": "scan", "L": L, "n": b.n, "h": h, "R": R, "nev": nev,
                    "nconv_min": int(res.nconv.min()), "seconds": round(dt, 1),
@@ -143,7 +157,7 @@ def disorder_scan(Ls, hs, R=32, nev=20, first_seed=0):
                    "S_mean": float(np.nanmean(ss)), "S_std": float(np.nanstd(ss)),
                    "S_rmt": float(0.5 * math.log(2) * L + 0.5 * math.log(0.5) - 0.25),
                    "z2_mean": float(np.nanmean(zz)), "z2_std": float(np.nanstd(zz)),
-                   "two_over_n": 2.0 / b.n}
+                   "two_over_n": 2.0 / b.n, "realizations": per}
         del bt
 
 
