@@ -1,7 +1,11 @@
 """Writes the stored expected values under tests/golden/ from the CPU oracle.
 
 Only ``oracle`` and the seeded input generators are used. Run from the
-repository root:  python tests/golden/make_golden.py
+repository root:
+
+    python tests/golden/make_golden.py            (the L = 14 dense reference)
+    python tests/golden/make_golden.py --si 16    (sparse shift-invert, L = 16)
+    python tests/golden/make_golden.py --si 18    (the same at L = 18, ~20 min)
 """
 import json
 import os
@@ -38,7 +42,42 @@ def plain(L, h, seed, nev):
     }
 
 
+def shift_invert(L, h, seed, nev, window):
+    """sigma = (E_min + E_max) / 2 from the oracle's extremal eigenvalues, the
+    `window` eigenvalues nearest sigma from the oracle's sparse shift-invert
+    solver (for the gaps of the selected pairs), the nev nearest of them with
+    the twist overlaps of their eigenvectors."""
+    f = disorder_fields(L, h, seed)
+    H = model.hamiltonian_csr(L, f)
+    emin, emax = lanczos.extremal_eigenvalues(H)
+    sigma = 0.5 * (emin + emax)
+    w, V = lanczos.eigenpairs_shift_invert_sparse(H, sigma, window)
+    sel = lanczos.select_nearest(w, sigma, nev)
+    E, U = w[sel], V[:, sel]
+    z = twist.twist_overlap(L, U)
+    res = lanczos.eigen_residuals(H, E, U)
+    return {
+        "L": L, "h": h, "seed": seed, "nev": nev,
+        "fields": f.tolist(),
+        "E_min": float(emin), "E_max": float(emax), "sigma": float(sigma),
+        "evals": E.tolist(), "window": w.tolist(),
+        "z_re": np.real(z).tolist(), "z_im": np.imag(z).tolist(),
+        "oracle_residuals": res.tolist(),
+        "source": "oracle sparse shift-invert (oracle.lanczos.eigenpairs_shift_invert_sparse, "
+                  f"{window} eigenvalues nearest sigma), extremes by "
+                  "oracle.lanczos.extremal_eigenvalues, twist by oracle.twist",
+    }
+
+
 if __name__ == "__main__":
+    if "--si" in sys.argv:
+        L = int(sys.argv[sys.argv.index("--si") + 1])
+        out = shift_invert(L, 3.0, 0, 6, 12)
+        name = f"si_L{L}_h3_seed0.json"
+        with open(os.path.join(HERE, name), "w") as fh:
+            json.dump(out, fh, indent=1)
+        print("wrote", name, out["sigma"], out["evals"])
+        sys.exit(0)
     out = plain(14, 3.0, 0, 10)
     with open(os.path.join(HERE, "plain_L14_h3_seed0.json"), "w") as fh:
         json.dump(out, fh, indent=1)
