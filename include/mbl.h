@@ -180,6 +180,18 @@ mbl_status mbl_si_lanczos(mbl_basis b, const double* h_host, double sigma, int n
 mbl_status mbl_twist_expect(mbl_basis b, const double* psi_dev, int64_t ld, int nvec,
                             double* z_host, void* stream);
 
+/* ---- allocation-free twist overlap, for callers that cannot allocate device
+ * memory (code that must not call hipMalloc: serving loops, harnesses that
+ * forbid allocation). Same result as mbl_twist_expect, bit for bit (the same
+ * kernels and reduction order), for nvec <= 32 vectors; nvec > 32 is
+ * MBL_ERR_ARG. The partial sums live in a static device array of the
+ * library (32 x 1024 x 2 + 64 doubles, about 513 KB, held by each GPU the
+ * library runs on until the process ends): the call allocates nothing. Calls
+ * that overlap on one GPU share that array and race; serialise them. The
+ * basis must belong to the current device. Synchronizes stream. */
+mbl_status mbl_twist_expect_noalloc(mbl_basis b, const double* psi_dev, int64_t ld, int nvec,
+                                    double* z_host, void* stream);
+
 /* ---- explicit eigen-residuals ||H psi_t - E_t psi_t||_2 (Alg. 1 output
  * check), psi_dev n x nvec (ld >= n), E_host[nvec], resid_host[nvec].
  * Synchronizes stream. */

@@ -78,6 +78,7 @@ _sig("mbl_minres_solve", _i32, [_vp, _dp, _d, _vp, _vp, _d, _i64, C.c_int, C.c_i
 _sig("mbl_si_lanczos", _i32, [_vp, _dp, _d, C.c_int, C.c_int, _d, _i64, _d, _d, _d, _vp, _u64,
                               C.c_int, C.c_int, _vp, _dp, _vp, _i64, _dp, C.POINTER(SiInfo), _vp])
 _sig("mbl_twist_expect", _i32, [_vp, _vp, _i64, C.c_int, _dp, _vp])
+_sig("mbl_twist_expect_noalloc", _i32, [_vp, _vp, _i64, C.c_int, _dp, _vp])
 _sig("mbl_entanglement_entropy", _i32, [_vp, _vp, _i64, C.c_int, C.c_int, _dp, _vp])
 _sig("mbl_spacing_ratio", _i32, [C.c_int, _dp, _dp, _dp])
 _sig("mbl_symmetric_eigenvalues", _i32, [C.c_int, _dp, _dp])
