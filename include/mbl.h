@@ -319,6 +319,48 @@ mbl_status mbl_si_lanczos_batched(mbl_basis b, mbl_batch w, const double* h_host
 mbl_status mbl_twist_expect_batched(mbl_basis b, mbl_batch w, const double* psi_dev, int nvec,
                                     double* z_host, void* stream);
 
+/* ---- many disorder realizations of uneven chain length in one call --------
+ * The disorder averages of Sec. IV need the eigenpairs nearest sigma of many
+ * realizations, each with its own L, fields and shift. Every problem is
+ * solved as by mbl_si_lanczos (Alg. 1 with Alg. 2 inner solves, FP64, the
+ * same stopping rule), with its Ritz vectors, explicit residuals and twist
+ * overlaps (Sec. III). Problems with L <= 18 run in one persistent launch
+ * (replayed from a captured graph): each workgroup claims a problem from a
+ * device counter and runs sigma, the Lanczos steps with their MINRES solves,
+ * the reorthogonalisation, the tridiagonal eigensolver, the Ritz extraction,
+ * residuals and twist on the device; problems with L >= 20 run as lockstep
+ * batches of one L (the batched form below), grouped inside the call.
+ * Per problem (inputs): L (even, 4..32), nev (1..min(32, C(L, L/2))),
+ * h_host (L fields), sigma (NaN: (E_min + E_max)/2 computed here, Sec. IV A),
+ * escale (> 0: energy scale of the stopping rule; else max(|E_min|, |E_max|)
+ * when sigma is computed, else a Gershgorin bound on ||H||), evecs_dev (n x nev
+ * column-major, ld = n, on the current device). Outputs: evals_host (nev,
+ * ascending), resid_host (nev, may be NULL), z_host (2 nev: Re, Im; may be
+ * NULL), sigma_out, info (info.seconds is the wall time of the whole call),
+ * status (that problem's mbl_si_lanczos status). mmax: 0 = 3 nev + 40 per
+ * problem, else 1..128 for all. Returns MBL_ERR_ARG before any launch on a
+ * bad argument, MBL_OK if every problem converged, else MBL_WARN_NOCONV (or
+ * MBL_WARN_BREAKDOWN) with the per-problem status set. Allocates its working
+ * memory for the call (per workgroup: 8 + mmax + 1 n-vectors) and frees it.
+ * Synchronizes stream. */
+typedef struct {
+  int32_t L;
+  int32_t nev;
+  const double* h_host;
+  double sigma;
+  double escale;
+  double* evecs_dev;
+  double* evals_host;
+  double* resid_host;
+  double* z_host;
+  double sigma_out;
+  mbl_si_info info;
+  mbl_status status;
+} mbl_problem;
+mbl_status mbl_si_lanczos_problems(mbl_problem* probs, int nprob, int mmax, double minres_tol,
+                                   int64_t minres_kmax, double eig_tol, double gap_tol,
+                                   uint64_t seed, int precond, void* stream);
+
 /* ---- small device helpers used by the bindings and tests ---------------- */
 /* out_host = sum_i x_i * y_i over n doubles, reduced in a fixed order. */
 mbl_status mbl_dot(int64_t n, const double* x_dev, const double* y_dev, double* out_host,

@@ -10,6 +10,7 @@ built (``python paper_2203_09732_amd/build.py``).
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 from dataclasses import dataclass
 
@@ -559,6 +560,75 @@ def twist_expect_batched(basis: Basis, batch: Batch, U, stream=None) -> np.ndarr
 # ---------------------------------------------------------------- derivatives
 _sig("mbl_eig_grad", _i32, [_vp, _dp, _d, _vp, _d, _i64, C.c_int, _vp, _dp, _dp, _dp,
                             C.POINTER(MinresInfo), _vp])
+
+
+class Problem(C.Structure):
+    """mbl_problem of include/mbl.h."""
+    _fields_ = [("L", C.c_int32), ("nev", C.c_int32), ("h_host", _dp), ("sigma", C.c_double),
+                ("escale", C.c_double), ("evecs_dev", _vp), ("evals_host", _dp),
+                ("resid_host", _dp), ("z_host", _dp), ("sigma_out", C.c_double),
+                ("info", SiInfo), ("status", C.c_int32)]
+
+
+_sig("mbl_si_lanczos_problems", _i32, [C.POINTER(Problem), C.c_int, C.c_int, _d, _i64, _d, _d,
+                                       _u64, C.c_int, _vp])
+
+
+@dataclass
+class ProblemResult:
+    L: int
+    status: int
+    evals: np.ndarray
+    evecs: object          # torch (n, nev) view of column-major storage
+    resid: np.ndarray
+    z: np.ndarray
+    sigma: float
+    steps: int
+    nconv: int
+    minres_iters: int
+    max_rel_resid: float
+    seconds: float
+
+
+def si_lanczos_problems(problems, mmax: int = 0, minres_tol: float = 1e-12,
+                        minres_kmax: int = 10_000_000, eig_tol: float = 1e-10,
+                        gap_tol: float = 1e-5, seed: int = 0, precond: str = "row", stream=None):
+    """Eigenpairs nearest sigma of many realizations of uneven L in one call
+    (mbl_si_lanczos_problems). problems: sequence of dicts with keys L, h, nev
+    and optionally sigma (default: the spectral midpoint, computed) and
+    escale. Returns (status, [ProblemResult])."""
+    import torch
+    keep, arr = [], (Problem * len(problems))()
+    out = []
+    for i, p in enumerate(problems):
+        L, nev = int(p["L"]), int(p["nev"])
+        n = math.comb(L, L // 2)
+        ha, hp = _f64(p["h"])
+        if ha.shape[0] != L:
+            raise ValueError("h must hold L fields")
+        store = torch.empty((nev, n), dtype=torch.float64, device="cuda")
+        ev, rs, zz = np.zeros(nev), np.zeros(nev), np.zeros(2 * nev)
+        keep += [ha, store, ev, rs, zz]
+        a = arr[i]
+        a.L, a.nev, a.h_host = L, nev, hp
+        a.sigma = float(p.get("sigma", float("nan")))
+        a.escale = float(p.get("escale", 0.0))
+        a.evecs_dev = store.data_ptr()
+        a.evals_host, a.resid_host, a.z_host = (ev.ctypes.data_as(_dp), rs.ctypes.data_as(_dp),
+                                                zz.ctypes.data_as(_dp))
+        out.append((store, ev, rs, zz))
+    st = lib.mbl_si_lanczos_problems(arr, len(problems), int(mmax), float(minres_tol),
+                                     int(minres_kmax), float(eig_tol), float(gap_tol),
+                                     int(seed) & (2**64 - 1), PRECOND[precond], _stream(stream))
+    _check(st, "mbl_si_lanczos_problems")
+    res = []
+    for i, (store, ev, rs, zz) in enumerate(out):
+        a = arr[i]
+        res.append(ProblemResult(int(a.L), int(a.status), ev, store.t(), rs, zz[0::2] + 1j * zz[1::2],
+                                 float(a.sigma_out), int(a.info.steps), int(a.info.nconv),
+                                 int(a.info.minres_iters), float(a.info.max_rel_resid),
+                                 float(a.info.seconds)))
+    return st, res
 
 
 def eig_grad(basis: Basis, h, E: float, psi, tol: float = 1e-10, kmax: int = 10_000_000,

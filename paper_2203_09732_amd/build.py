@@ -33,7 +33,7 @@ COMMON = [
 ]
 
 SOURCES = ["kernels.hip", "minres.hip", "lanczos.hip", "batched.hip", "adjoint.hip", "schmidt.hip",
-           "noalloc.hip", "api.hip"]
+           "noalloc.hip", "wgsolve.hip", "api.hip"]
 
 
 def _compile(src: str) -> str:
