@@ -24,7 +24,8 @@ def torch():
     return t
 
 
-def test_campaign_uneven_lengths_and_resume(gpu, torch, tmp_path):
+@pytest.mark.parametrize("mode", ["persistent", "lockstep"])
+def test_campaign_uneven_lengths_and_resume(gpu, torch, tmp_path, mode):
     from paper_2203_09732_amd import campaign
     tasks = []
     for i in range(6):
@@ -32,8 +33,8 @@ def test_campaign_uneven_lengths_and_resume(gpu, torch, tmp_path):
         h = [2.0, 3.0, 4.0][i % 3]
         tasks.append(campaign.Task(i, L, h, disorder_fields(L, h, 100 + i)))
     path = str(tmp_path / "res.jsonl")
-    say("campaign L in {12, 14}, 6 realizations, nev=2")
-    recs = campaign.run(tasks, nev=2, results_path=path, log=say)
+    say(f"campaign ({mode}) L in {{12, 14}}, 6 realizations, nev=2")
+    recs = campaign.run(tasks, nev=2, results_path=path, log=say, mode=mode)
     assert len(recs) == 6
     for rec in recs:
         t = tasks[rec["index"]]
@@ -48,7 +49,7 @@ def test_campaign_uneven_lengths_and_resume(gpu, torch, tmp_path):
         zr = twist.twist_overlap(t.L, V)
         assert np.abs(z - zr).max() <= 1e-6
     # a second run finds every realization in the results file and does nothing
-    again = campaign.run(tasks, nev=2, results_path=path, log=None)
+    again = campaign.run(tasks, nev=2, results_path=path, log=None, mode=mode)
     assert again == []
     assert len(open(path).read().strip().splitlines()) == 6
 
