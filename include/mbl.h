@@ -324,12 +324,14 @@ mbl_status mbl_twist_expect_batched(mbl_basis b, mbl_batch w, const double* psi_
  * realizations, each with its own L, fields and shift. Every problem is
  * solved as by mbl_si_lanczos (Alg. 1 with Alg. 2 inner solves, FP64, the
  * same stopping rule), with its Ritz vectors, explicit residuals and twist
- * overlaps (Sec. III). Problems with L <= 18 run in one persistent launch
+ * overlaps (Sec. III). Problems with L <= 16 run in one persistent launch
  * (replayed from a captured graph): each workgroup claims a problem from a
  * device counter and runs sigma, the Lanczos steps with their MINRES solves,
  * the reorthogonalisation, the tridiagonal eigensolver, the Ritz extraction,
- * residuals and twist on the device; problems with L >= 20 run as lockstep
- * batches of one L (the batched form below), grouped inside the call.
+ * residuals and twist on the device; problems with L >= 18 run as lockstep
+ * batches of one L (the batched form below, up to 32 realizations, sigma
+ * found per realization first), grouped inside the call after the
+ * persistent launch.
  * Per problem (inputs): L (even, 4..32), nev (1..min(32, C(L, L/2))),
  * h_host (L fields), sigma (NaN: (E_min + E_max)/2 computed here, Sec. IV A),
  * escale (> 0: energy scale of the stopping rule; else max(|E_min|, |E_max|)

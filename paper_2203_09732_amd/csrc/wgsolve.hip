@@ -5,16 +5,21 @@
 //
 // Workgroups claim problems from a device counter (atomicAdd) until the queue
 // is empty, so every workgroup reaches the exit and the grid drains. A
-// workgroup (16 waves) keeps every vector of its realization in its own slot
+// workgroup (8 waves) keeps every vector of its realization in its own slot
 // of device memory and every scalar in registers or LDS; the reductions are
 // workgroup reductions (LDS, fixed order), so there is no grid barrier and no
-// host round trip between the steps. At L <= 16 a realization's MINRES
-// vectors fit its share of the XCD's L2 (32 workgroups x 10 vectors of
-// 103 KB at L = 16 in 4 MB); at L = 18 they stream from the last-level cache
-// and HBM. The solver is inlined into the kernel for each chain length (the
-// problem's basis selects the instance), so every problem-wide value stays in
-// scalar registers; it needs 229 VGPRs, so a workgroup is 512 threads and a
-// CU runs one.
+// host round trip between the steps. The launch serves L <= kWgMaxL = 16:
+// there the MINRES vectors of all realizations in flight (256 x 10 x 103 KB
+// at L = 16) about fill the last-level cache, so most gathers of a neighbour
+// amplitude hit it. At L = 18 they are about 0.7 GB; a gather then fetches a
+// whole line from HBM for one double, and a mixed set of 171 realizations
+// had mostly not finished after 800 s, where a lockstep batch of 32 (whose
+// interleaved layout turns each gather into 256 contiguous bytes) takes
+// about 7 s of the whole chip per realization. Longer chains therefore go to
+// the lockstep batches inside the same call. The solver is inlined into the
+// kernel for each chain length (the problem's basis selects the instance), so
+// every problem-wide value stays in scalar registers; it needs 229 VGPRs, so
+// a workgroup is 512 threads and a CU runs one.
 //
 // Per realization:
 //  1. sigma = (E_min + E_max) / 2 (Sec. IV A) unless given: Lanczos on H
@@ -39,6 +44,7 @@
 #include <map>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <vector>
 
 namespace mbl {
@@ -49,6 +55,7 @@ constexpr int kWgMaxNev = 32;
 constexpr int kWgMaxM = 128;          // Lanczos steps per realization
 constexpr int kWgSigmaSteps = 320;    // Lanczos steps of the sigma search
 constexpr int kWgVecs = 8;            // MINRES vectors in a slot
+constexpr int kWgMaxL = 16;           // longest chain of the persistent launch
 
 struct WgProblem {
   double h[kMaxL];
@@ -81,6 +88,7 @@ struct WgParams {
   int64_t slot_stride;      // doubles per workgroup slot
   int64_t vs;               // doubles per n-vector inside a slot (>= max n)
   unsigned int* counter;
+  unsigned int* done;       // host-mapped, one per workgroup: realizations it finished
   int nprob;
   int precond;
   double minres_tol, eig_tol, gap_tol, sigma_rel_tol;
@@ -760,12 +768,13 @@ __device__ __attribute__((always_inline)) void wg_solve(const WgParams& P, const
   __syncthreads();
 }
 
-#define MBL_WG_SPLITS(X) X(12, 9) X(14, 10) X(16, 10) X(18, 12)
+#define MBL_WG_SPLITS(X) X(12, 9) X(14, 10) X(16, 10)
 
 __global__ __launch_bounds__(kWgThreads) void k_si_campaign(WgParams P) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ WgShared S;
   double* slot = P.slots + (size_t)blockIdx.x * P.slot_stride;
+  unsigned int finished = 0;
   for (;;) {
     if (threadIdx.x == 0) S.pid = (int)atomicAdd(P.counter, 1u);
     __syncthreads();
@@ -786,6 +795,9 @@ __global__ __launch_bounds__(kWgThreads) void k_si_campaign(WgParams P) {
         wg_solve<0, 0>(P, pr, res, slot, S, smem);
         break;
     }
+    ++finished;
+    if (threadIdx.x == 0 && P.done)   // a plain store to this workgroup's own slot
+      __hip_atomic_store(P.done + blockIdx.x, finished, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
   }
 }
 
@@ -924,6 +936,25 @@ static mbl_status campaign_small(mbl_problem* probs, const std::vector<int>& idx
   P.slot_stride = slot_stride;
   P.vs = vs;
   P.counter = static_cast<unsigned int*>(d_cnt.p);
+  // progress counter in host-mapped pinned memory
+  unsigned int* done_host = nullptr;
+  struct HostGuard {
+    unsigned int*& p;
+    ~HostGuard() {
+      if (p) (void)hipHostFree(p);
+    }
+  } hguard{done_host};
+  if (hipHostMalloc((void**)&done_host, sizeof(unsigned int) * G, hipHostMallocMapped) != hipSuccess) {
+    (void)hipGetLastError();
+    done_host = nullptr;
+  }
+  P.done = nullptr;
+  if (done_host) {
+    for (int g = 0; g < G; ++g) done_host[g] = 0;
+    void* dp = nullptr;
+    if (hipHostGetDevicePointer(&dp, done_host, 0) == hipSuccess) P.done = static_cast<unsigned int*>(dp);
+    else (void)hipGetLastError();
+  }
   P.nprob = nprob;
   P.precond = precond;
   P.minres_tol = minres_tol;
@@ -950,7 +981,38 @@ static mbl_status campaign_small(mbl_problem* probs, const std::vector<int>& idx
   if (graph) (void)hipGraphDestroy(graph);
   MBL_HIP(e);
   e = hipGraphLaunch(exec, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  // wait for the launch; with MBL_VERBOSE set, report the realizations done
+  // (counted by the kernel in host-mapped memory) every 30 s
+  if (e == hipSuccess) {
+    const bool verbose = std::getenv("MBL_VERBOSE") != nullptr;
+    hipEvent_t ev = nullptr;
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(ev, s);
+    const auto t0 = std::chrono::steady_clock::now();
+    auto last = t0;
+    while (e == hipSuccess) {
+      const hipError_t q = hipEventQuery(ev);
+      if (q == hipSuccess) break;
+      if (q != hipErrorNotReady) {
+        e = q;
+        break;
+      }
+      std::this_thread::sleep_for(std::chrono::milliseconds(20));
+      const auto now = std::chrono::steady_clock::now();
+      if (verbose && done_host && std::chrono::duration<double>(now - last).count() >= 30.0) {
+        last = now;
+        unsigned int total = 0;
+        for (int g = 0; g < G; ++g) total += __atomic_load_n(done_host + g, __ATOMIC_RELAXED);
+        std::fprintf(stderr, "[mbl] problems: %u of %d done (%.0f s)\n", total, nprob,
+                     std::chrono::duration<double>(now - t0).count());
+      }
+    }
+    if (ev) (void)hipEventDestroy(ev);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (verbose && e == hipSuccess)
+      std::fprintf(stderr, "[mbl] persistent launch: %d problems in %.1f s\n", nprob,
+                   std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count());
+  }
   (void)hipGraphExecDestroy(exec);
   MBL_HIP(e);
   std::vector<WgResult> hr(hp.size());
@@ -1112,7 +1174,7 @@ extern "C" mbl_status mbl_si_lanczos_problems(mbl_problem* probs, int nprob, int
     m = (int)std::min<uint64_t>((uint64_t)m, n);
     MBL_ARG(m >= pr.nev, "mmax must be >= nev");
     mm[i] = m;
-    (pr.L <= 18 ? small : large).push_back(i);
+    (pr.L <= kWgMaxL ? small : large).push_back(i);
   }
   for (int i = 0; i < nprob; ++i) {
     probs[i].status = MBL_OK;

@@ -1,7 +1,8 @@
 """Many realizations of uneven chain length in one call
-(mbl_si_lanczos_problems): the persistent per-workgroup solver (L <= 18)
+(mbl_si_lanczos_problems): the persistent per-workgroup solver (L <= 16)
 against the oracle's dense eigenpairs, the stored L = 16 sparse reference and
-the single-realization path.
+the single-realization path; the lockstep batches the call runs for L >= 18
+against the stored L = 18 sparse reference, in a call that mixes both.
 
 Bars as for mbl_si_lanczos: sigma and the extremes 1e-10 relative; eigenvalues
 |E - E_ref| / max(|E_ref|, 1) <= 1e-10; 1 - |<u, u_ref>| <= 1e-10; explicit
@@ -81,6 +82,31 @@ def test_given_shift_and_single_path_agree(gpu):
     assert res[0].steps == single.steps
 
 
+def _check_stored(g, r):
+    """A result against a stored sparse reference: eigenvalues, the oracle's
+    CSR residual and the Davis-Kahan overlap bound with the stored gaps."""
+    L, nev = g["L"], g["nev"]
+    f = np.array(g["fields"])
+    escale = max(abs(g["E_min"]), abs(g["E_max"]))
+    say(f"  L={L} steps={r.steps} minres={r.minres_iters} sigma={r.sigma:.12f} t={r.seconds:.1f}s")
+    assert r.status == 0 and r.nconv == nev
+    assert abs(r.sigma - g["sigma"]) <= 1e-10 * escale
+    Eref = np.array(g["evals"])
+    assert np.all(np.abs(r.evals - Eref) / np.maximum(np.abs(Eref), 1) <= 1e-10)
+    U = r.evecs.cpu().numpy()
+    rr = lanczos.eigen_residuals(model.hamiltonian_csr(L, f), r.evals, U)
+    assert np.all(rr <= 1e-10 * escale)
+    assert np.allclose(r.resid, rr, rtol=1e-6, atol=1e-14)
+    spec = np.array(g["window"])
+    delta = np.array([np.min(np.abs(np.delete(spec, np.argmin(np.abs(spec - e))) - e))
+                      for e in r.evals])
+    deficit = 1 - np.sqrt(1 - np.minimum(1.0, rr / delta) ** 2)
+    assert np.all(deficit <= 1e-10)
+    zref = np.array(g["z_re"]) + 1j * np.array(g["z_im"])
+    assert np.all(np.abs(r.z - zref) <= 2 * np.sqrt(2 * deficit) + 1e-12)
+    assert np.abs(r.z - twist.twist_overlap(L, U)).max() <= 1e-13
+
+
 def test_L16_against_stored_sparse_reference(gpu):
     g = json.load(open(os.path.join(HERE, "golden", "si_L16_h3_seed0.json")))
     L, nev = g["L"], g["nev"]
@@ -89,23 +115,31 @@ def test_L16_against_stored_sparse_reference(gpu):
     probs = [dict(L=L, h=f, nev=nev, sigma=g["sigma"], escale=escale), dict(L=L, h=f, nev=nev)]
     st, res = gpu.si_lanczos_problems(probs, seed=9, minres_kmax=400_000)
     assert st == 0
-    H = model.hamiltonian_csr(L, f)
-    Eref = np.array(g["evals"])
     for r in res:
-        say(f"  L=16 steps={r.steps} minres={r.minres_iters} sigma={r.sigma:.12f} t={r.seconds:.1f}s")
-        assert r.status == 0 and r.nconv == nev
-        assert abs(r.sigma - g["sigma"]) <= 1e-10 * escale
-        assert np.all(np.abs(r.evals - Eref) / np.maximum(np.abs(Eref), 1) <= 1e-10)
-        U = r.evecs.cpu().numpy()
-        rr = lanczos.eigen_residuals(H, r.evals, U)
-        assert np.all(rr <= 1e-10 * escale)
-        spec = np.array(g["window"])
-        delta = np.array([np.min(np.abs(np.delete(spec, np.argmin(np.abs(spec - e))) - e))
-                          for e in r.evals])
-        deficit = 1 - np.sqrt(1 - np.minimum(1.0, rr / delta) ** 2)
-        assert np.all(deficit <= 1e-10)
-        zref = np.array(g["z_re"]) + 1j * np.array(g["z_im"])
-        assert np.all(np.abs(r.z - zref) <= 2 * np.sqrt(2 * deficit) + 1e-12)
+        _check_stored(g, r)
+
+
+def test_L18_lockstep_route_in_a_mixed_call(gpu):
+    """L = 18 (stored reference, sigma computed by the call) beside an L = 12
+    realization of the persistent launch and a second L = 18 realization of
+    other fields that shares the lockstep batch."""
+    g = json.load(open(os.path.join(HERE, "golden", "si_L18_h3_seed0.json")))
+    f = np.array(g["fields"])
+    probs = [dict(L=12, h=disorder_fields(12, 3.0, 41), nev=4),
+             dict(L=18, h=f, nev=g["nev"]),
+             dict(L=18, h=disorder_fields(18, 4.0, 42), nev=2)]
+    st, res = gpu.si_lanczos_problems(probs, seed=13, minres_kmax=2_000_000)
+    assert st == 0
+    _check_dense(12, probs[0]["h"], res[0], 4)
+    _check_stored(g, res[1])
+    r = res[2]
+    assert r.status == 0 and r.nconv == 2 and r.L == 18
+    H = model.hamiltonian_csr(18, probs[2]["h"])
+    rr = lanczos.eigen_residuals(H, r.evals, r.evecs.cpu().numpy())
+    lo, hi = lanczos.extremal_eigenvalues(H)
+    escale = max(abs(lo), abs(hi))
+    assert abs(r.sigma - 0.5 * (lo + hi)) <= 1e-10 * escale
+    assert np.all(rr <= 1e-10 * escale)
 
 
 def test_problem_array_rejects_bad_arguments(gpu):
