@@ -305,8 +305,9 @@ mbl_status mbl_minres_solve_batched(mbl_basis b, mbl_batch w, const double* h_ho
  * side is zeroed). Outputs: evals_host[R * nev] (realization-major,
  * ascending per realization), evecs_dev: nev interleaved blocks of n * R
  * doubles (block t holds pair t of every realization), resid_host[R * nev]
- * explicit FP64 residuals, info_host[R] (info_host[0].minres_iters holds the
- * batch total). Synchronizes. */
+ * explicit FP64 residuals, info_host[R] (minres_iters: the iterations that
+ * realization's own solves took; the batch launches, per Lanczos step, as
+ * many as its slowest realization). Synchronizes. */
 mbl_status mbl_si_lanczos_batched(mbl_basis b, mbl_batch w, const double* h_host,
                                   const double* sigma_host, int nev, int mmax, double minres_tol,
                                   int64_t minres_kmax, double eig_tol, double gap_tol,

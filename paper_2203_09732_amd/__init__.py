@@ -505,9 +505,10 @@ class BatchEigResult:
     resid: np.ndarray        # (R, nev)
     steps: np.ndarray        # (R,)
     nconv: np.ndarray        # (R,)
-    minres_iters: int        # whole batch
+    minres_iters: int        # whole batch: the sum of per_realization_iters
     max_rel_resid: np.ndarray
     seconds: float
+    per_realization_iters: np.ndarray   # (R,) each realization's own MINRES iterations
 
 
 def si_lanczos_batched(basis: Basis, batch: Batch, fields, sigmas, nev: int, mmax: int | None = None,
@@ -538,8 +539,9 @@ def si_lanczos_batched(basis: Basis, batch: Batch, fields, sigmas, nev: int, mma
     _check(st, "mbl_si_lanczos_batched")
     return BatchEigResult(st, evals.reshape(R, nev), U, resid.reshape(R, nev),
                           np.array([i.steps for i in info]), np.array([i.nconv for i in info]),
-                          int(info[0].minres_iters), np.array([i.max_rel_resid for i in info]),
-                          float(info[0].seconds))
+                          int(sum(i.minres_iters for i in info)),
+                          np.array([i.max_rel_resid for i in info]), float(info[0].seconds),
+                          np.array([i.minres_iters for i in info], dtype=np.int64))
 
 
 def twist_expect_batched(basis: Basis, batch: Batch, U, stream=None) -> np.ndarray:

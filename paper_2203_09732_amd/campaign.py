@@ -12,7 +12,9 @@ Two ways to run them:
   batches of R realizations (a power of two, as large as the kernels' LDS
   budget allows for that L) by the lockstep shift-invert Lanczos, after sigma
   has been found for each realization. A batch that is not full is padded
-  with copies of its last realization, whose results are dropped.
+  with copies of its last realization, whose results are dropped. Within a
+  chain length the realizations are ordered by their mean square field (the
+  cost proxy the library's problem-array call uses too).
 
 One JSON line per realization is appended to an optional results file;
 realizations already present there are skipped, so an interrupted campaign
@@ -111,7 +113,9 @@ def _run_lockstep(todo, nev, results_path, precision, minres_tol, eig_tol, gap_t
     import torch
     records = []
     for L in sorted({t.L for t in todo}):
-        group = [t for t in todo if t.L == L]
+        # similar disorder strength in one batch: a batch runs as many MINRES
+        # iterations per step as its slowest realization needs
+        group = sorted((t for t in todo if t.L == L), key=lambda t: float(np.mean(t.fields ** 2)))
         R = widest_batch(L, min(max_R, len(group)))
         while True:       # narrower batches if the split's tables leave too little LDS
             basis = Basis(L, tune.best_lo_bits(L, R, precision))

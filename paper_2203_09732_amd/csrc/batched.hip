@@ -1082,8 +1082,8 @@ static mbl_status bsi_lanczos_run(mbl_basis_s* b, mbl_batch_s* bw, const double*
   std::vector<std::vector<int>> sel(R);
   std::vector<int> active(R, 1), ksteps(R, 0);
   std::vector<double> beta_k(R, 0.0);
-  int64_t total_iters = 0;
-  std::vector<int64_t> its;
+  int64_t total_iters = 0, lockstep_iters = 0;
+  std::vector<int64_t> its, rits(R, 0);
   std::vector<double> phis;
   int k = 0;
   std::vector<double> alpha(R), bb(R), nav(R);
@@ -1092,7 +1092,13 @@ static mbl_status bsi_lanczos_run(mbl_basis_s* b, mbl_batch_s* bw, const double*
     MBL_TRY(bupload(bw, h, sigma, s));
     MBL_TRY(bminres_run(b, bw, precision, precond, vk, bw->x, minres_tol, minres_kmax, active, s,
                         its, phis));
-    for (int r = 0; r < R; ++r) total_iters += its[r];
+    int64_t most = 0;
+    for (int r = 0; r < R; ++r) {
+      total_iters += its[r];
+      rits[r] += its[r];
+      most = std::max(most, its[r]);
+    }
+    lockstep_iters += most;   // the iterations the batch launched for this step
     // w = x - beta_k v_{k-1}
     MBL_HIP(hipMemcpyAsync(bw->w, bw->x, sizeof(double) * NR, hipMemcpyDeviceToDevice, s));
     if (k > 1) {
@@ -1170,7 +1176,8 @@ static mbl_status bsi_lanczos_run(mbl_basis_s* b, mbl_batch_s* bw, const double*
       int live = 0;
       for (int r = 0; r < R; ++r) live += active[r];
       std::fprintf(stderr, "[mbl] batched si_lanczos step %d: %d of %d realizations still "
-                   "stepping, minres total %lld\n", k, live, R, (long long)total_iters);
+                   "stepping, minres total %lld, lockstep %lld\n", k, live, R,
+                   (long long)total_iters, (long long)lockstep_iters);
     }
     if (all_conv) break;
   }
@@ -1230,12 +1237,11 @@ static mbl_status bsi_lanczos_run(mbl_basis_s* b, mbl_batch_s* bw, const double*
     if (info) {
       info[r].steps = ksteps[r];
       info[r].nconv = nconv;
-      info[r].minres_iters = 0;
+      info[r].minres_iters = rits[r];
       info[r].max_rel_resid = mx;
       info[r].seconds = secs;
     }
   }
-  if (info) info[0].minres_iters = total_iters;
   if (!all_ok) {
     set_error("some batched eigenpairs did not converge");
     return MBL_WARN_NOCONV;

@@ -853,6 +853,14 @@ static uint64_t nchoosek(int n, int k) {
 
 // Problems with L <= kWgMaxL: one persistent launch, one realization per
 // workgroup, claimed from a device counter.
+// Mean square field of a realization: the width of its spectrum grows with
+// it, and the MINRES iterations per solve fall (a cost proxy for scheduling).
+static double disorder_strength(const mbl_problem& pr) {
+  double s2 = 0.0;
+  for (int j = 0; j < pr.L; ++j) s2 += pr.h_host[j] * pr.h_host[j];
+  return s2 / pr.L;
+}
+
 static mbl_status campaign_small(mbl_problem* probs, const std::vector<int>& idx,
                                  const std::vector<int>& mm, double minres_tol,
                                  int64_t minres_kmax, double eig_tol, double gap_tol,
@@ -893,9 +901,13 @@ static mbl_status campaign_small(mbl_problem* probs, const std::vector<int>& idx
     }
     hph.push_back(ph);
   }
-  // problems, most expensive first (longest chains claim workgroups first)
+  // problems, most expensive first: longest chains, then weakest disorder
+  // (a narrower spectrum, so smaller gaps at sigma and longer MINRES solves)
   std::vector<int> order(idx);
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return probs[a].L > probs[b].L; });
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+    if (probs[a].L != probs[b].L) return probs[a].L > probs[b].L;
+    return disorder_strength(probs[a]) < disorder_strength(probs[b]);
+  });
   std::vector<WgProblem> hp(order.size());
   int mmax_max = 1;
   for (size_t q = 0; q < order.size(); ++q) {
@@ -1041,13 +1053,20 @@ static mbl_status campaign_small(mbl_problem* probs, const std::vector<int>& idx
 }
 
 // Problems with L > kWgMaxL: lockstep batches of one chain length (the
-// batched form), up to 32 realizations, padded to a power of two.
+// batched form), up to 32 realizations, padded to a power of two. A batch
+// launches, per Lanczos step, as many MINRES iterations as its slowest
+// realization needs, so each chain length's problems are ordered by disorder
+// strength first and a batch holds realizations of similar cost.
 static mbl_status campaign_large(mbl_problem* probs, const std::vector<int>& idx,
                                  const std::vector<int>& mm, double minres_tol,
                                  int64_t minres_kmax, double eig_tol, double gap_tol,
                                  uint64_t seed, int precond, hipStream_t s) {
   std::map<int, std::vector<int>> byL;
   for (int i : idx) byL[probs[i].L].push_back(i);
+  for (auto& kv : byL)
+    std::stable_sort(kv.second.begin(), kv.second.end(), [&](int a, int c) {
+      return disorder_strength(probs[a]) < disorder_strength(probs[c]);
+    });
   for (auto& kv : byL) {
     const int L = kv.first;
     const std::vector<int>& all = kv.second;
