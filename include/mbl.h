@@ -329,10 +329,13 @@ mbl_status mbl_twist_expect_batched(mbl_basis b, mbl_batch w, const double* psi_
  * (replayed from a captured graph): each workgroup claims a problem from a
  * device counter and runs sigma, the Lanczos steps with their MINRES solves,
  * the reorthogonalisation, the tridiagonal eigensolver, the Ritz extraction,
- * residuals and twist on the device; problems with L >= 18 run as lockstep
- * batches of one L (the batched form below, up to 32 realizations, sigma
- * found per realization first), grouped inside the call after the
- * persistent launch.
+ * residuals and twist on the device. Problems with L >= 18 run after it,
+ * per L, in the streaming batched form: up to 32 lanes of one batch
+ * workspace share every MINRES launch, but each lane takes its own Lanczos
+ * steps (its solve restarted in flight on v_{k+1} when it ends) and, when
+ * its realization has converged, the next one (sigma found per realization
+ * first). The environment variable MBL_PERSISTENT_MAX_L (even, 4..16)
+ * lowers the longest chain of the persistent launch.
  * Per problem (inputs): L (even, 4..32), nev (1..min(32, C(L, L/2))),
  * h_host (L fields), sigma (NaN: (E_min + E_max)/2 computed here, Sec. IV A),
  * escale (> 0: energy scale of the stopping rule; else max(|E_min|, |E_max|)

@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <functional>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -289,6 +290,131 @@ __global__ void k_binit_state(const double* __restrict__ partials, int G, int R,
     s.done = s.bad || !(fabs(s.beta) >= tol && 0 < kmax);
     S0[r] = s;
   }
+}
+
+// ---- the streaming form: one realization's solve restarted in flight ----
+
+// MINRES restart of the realizations with mask[r] != 0 from x0 = 0: z_K =
+// src_r, z_{K-1} = 0, q_K = M_r^{-1} z_K, d = x = 0 (the buffers passed are
+// the ones iteration K uses); partial sums of q_K . z_K. Other realizations
+// are not touched.
+template <int L>
+__global__ __launch_bounds__(kBWG) void k_blane_init(DevBasis B, BatchDev Q, int kind,
+                                                     const int* __restrict__ mask,
+                                                     const double* __restrict__ src, double* zk,
+                                                     double* zkm1, double* qk, double* d0,
+                                                     double* d1, double* x,
+                                                     double* __restrict__ partials) {
+  const int R = Q.R;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const BTables t = bsetup(B, Q, smem);
+  __syncthreads();
+  const int lp = (threadIdx.x & 63) % (R >> 1);
+  const bool m0 = mask[2 * lp] != 0, m1 = mask[2 * lp + 1] != 0;
+  double a0 = 0, a1 = 0;
+  if (m0 || m1) {
+    bfor_rows(B, t, R, [&](uint32_t row, uint32_t, uint32_t, uint32_t, uint32_t, uint32_t a, int p) {
+      const size_t e = (size_t)row * R + 2 * p;
+      const int na = bnanti<L>(a);
+      double dg0, dg1;
+      bdiag2<L>(t, p, a, na, dg0, dg1);
+      if (m0) {
+        const double z = src[e], q = z / precond_value(kind, dg0, na);
+        zk[e] = z;
+        zkm1[e] = 0.0;
+        qk[e] = q;
+        d0[e] = 0.0;
+        d1[e] = 0.0;
+        x[e] = 0.0;
+        a0 += q * z;
+      }
+      if (m1) {
+        const double z = src[e + 1], q = z / precond_value(kind, dg1, na);
+        zk[e + 1] = z;
+        zkm1[e + 1] = 0.0;
+        qk[e + 1] = q;
+        d0[e + 1] = 0.0;
+        d1[e + 1] = 0.0;
+        x[e + 1] = 0.0;
+        a1 += q * z;
+      }
+    });
+  }
+  const double sm = bblock_sum(a0, a1, t.red, R);
+  if (threadIdx.x < R) partials[(size_t)blockIdx.x * R + threadIdx.x] = sm;
+}
+
+// One workgroup per realization: beta_1 and the initial state of each
+// restarted solve, marked fresh, into the slot that the Givens step of the
+// restart iteration reads (it carries the state on unchanged).
+__global__ void k_blane_state(const double* __restrict__ partials, int G, int R,
+                              const int* __restrict__ mask, double tol, int64_t kmax,
+                              BState* Sslot) {
+  __shared__ double red[kWavesPerWG];
+  const int r = blockIdx.x;
+  if (!mask[r]) return;
+  double v = 0;
+  for (int g = threadIdx.x; g < G; g += blockDim.x) v += partials[(size_t)g * R + r];
+  const double qz = block_sum_all(v, red);
+  if (threadIdx.x == 0) {
+    BState st{};
+    st.beta_prev = 1.0;
+    st.beta = sqrt(qz);
+    st.c = 1.0;
+    st.phi = st.beta;
+    st.k = 0;
+    st.bad = !isfinite(st.beta);
+    st.done = st.bad || !(fabs(st.beta) >= tol && 0 < kmax);
+    st.fresh = 1;
+    Sslot[r] = st;
+  }
+}
+
+// out[i, r] = V_{kidx[r]}[i, r] (0 where kidx[r] < 0)
+__global__ __launch_bounds__(kWG) void k_blane_gather(int64_t n, int R, const double* __restrict__ V,
+                                                      int64_t vstride, const int* __restrict__ kidx,
+                                                      double* __restrict__ out) {
+  const int64_t total = n * R;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = kidx[e & (R - 1)];
+    out[e] = c >= 0 ? V[(size_t)c * vstride + e] : 0.0;
+  }
+}
+
+// V_{kidx[r]}[i, r] = src[i, r] where kidx[r] >= 0
+__global__ __launch_bounds__(kWG) void k_blane_scatter(int64_t n, int R,
+                                                       const double* __restrict__ src, double* V,
+                                                       int64_t vstride,
+                                                       const int* __restrict__ kidx) {
+  const int64_t total = n * R;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = kidx[e & (R - 1)];
+    if (c >= 0) V[(size_t)c * vstride + e] = src[e];
+  }
+}
+
+// column `lane` of blocks 0 .. nblk - 1 of V set to 0, then block 0 of it to
+// src (contiguous n), if src is given
+__global__ __launch_bounds__(kWG) void k_blane_reset(int64_t n, int R, int lane, double* V,
+                                                     int64_t vstride, int nblk,
+                                                     const double* __restrict__ src) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const size_t e = (size_t)i * R + lane;
+    for (int c = 0; c < nblk; ++c) V[(size_t)c * vstride + e] = 0.0;
+    if (src) V[e] = src[i];
+  }
+}
+
+// dst (n contiguous) = column `lane` of src (interleaved n x R)
+__global__ __launch_bounds__(kWG) void k_blane_get(int64_t n, int R, int lane,
+                                                   const double* __restrict__ src,
+                                                   double* __restrict__ dst) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[(size_t)i * R + lane];
 }
 
 // The Givens step of the last issued iteration (one workgroup of kBWG
@@ -748,12 +874,30 @@ static mbl_status breduce_host(mbl_batch_s* bw, const double* partials, int G, i
   return MBL_OK;
 }
 
+// The streaming form's view of a running batched MINRES. After each chunk of
+// iterations has been issued, the hook receives the states after iteration
+// `iter` of an earlier chunk (the snapshot lags one chunk, so the d/x updates
+// of every realization done in it have been issued too) and `next_k`, the
+// iteration the next chunk starts with. It may restart the solve of any
+// realization that is done: restart[r] = 1 with right-hand side column r of
+// *rhs (x0 = 0, from iteration next_k on). keep_going = false ends the loop.
+struct MinresHook {
+  std::function<mbl_status(const BState* st, int64_t iter, int64_t next_k, std::vector<int>& restart,
+                           const double** rhs, bool& keep_going)>
+      on_snapshot;
+  int* mask_dev = nullptr;       // R ints, device
+  double* part_dev = nullptr;    // bgrid * R doubles, device
+};
+
 // Alg. 2 on all realizations, from x0 = 0 with z_1 = scale_r src_r (a zero
-// scale makes realization r done at once). x: T, n * R.
+// scale makes realization r done at once). x: T, n * R. With a hook (FP64
+// only), the loop runs until the hook stops it and per-realization solves are
+// restarted in flight.
 template <typename T>
 static mbl_status bminres_core(mbl_basis_s* b, mbl_batch_s* bw, const BatchDev& Q, int precond,
                                const double* src, const double* scale_dev, T* x, double tol,
-                               int64_t kmax, hipStream_t s, std::vector<BState>& fin) {
+                               int64_t kmax, hipStream_t s, std::vector<BState>& fin,
+                               MinresHook* hook = nullptr) {
   const int R = bw->R;
   const int64_t n = b->n;
   T* Z[2] = {(T*)bw->z[0], (T*)bw->z[1]};
@@ -857,19 +1001,64 @@ static mbl_status bminres_core(mbl_basis_s* b, mbl_batch_s* bw, const BatchDev& 
   int64_t issued = 0;
   int pending = 0, slot = 0;
   bool done = false;
+  int64_t snap_iter[2] = {0, 0};
+  // restart the realizations in `restart` at iteration K = issued + 1: z_K =
+  // rhs, z_{K-1} = 0, q_K = M^{-1} z_K, d = x = 0, and their initial state
+  // (marked fresh) in the slot the Givens step of iteration K reads
+  auto restart_lanes = [&](const std::vector<int>& restart, const double* rhs) -> mbl_status {
+    const int64_t K = issued + 1;
+    if (K % kDxGroup != 2 || kGraphIters % kRing != 0) {
+      set_error("internal: streaming restart off the iteration grid");
+      return MBL_ERR_NUMERIC;
+    }
+    MBL_HIP(hipMemcpyAsync(hook->mask_dev, restart.data(), sizeof(int) * R, hipMemcpyHostToDevice,
+                           s));
+    const size_t lds = blds_bytes(R, b->L, b->nlo);
+    const dim3 g(G), blk(kBWG);
+    const DevBasis B = b->dev();
+#define MBL_CASE(LL, NN)                                                                        \
+  case LL * 64 + NN:                                                                           \
+    hipLaunchKernelGGL((k_blane_init<LL>), g, blk, lds, s, B, Q, precond, hook->mask_dev, rhs, \
+                       (double*)Z[K & 1], (double*)Z[(K + 1) & 1], (double*)Qv[K % kRing],     \
+                       (double*)D[0], (double*)D[1], (double*)x, hook->part_dev);            \
+    break;
+    MBL_BDISPATCH(MBL_CASE)
+#undef MBL_CASE
+    MBL_HIP(hipGetLastError());
+    hipLaunchKernelGGL(k_blane_state, dim3(R), dim3(kWG), 0, s, hook->part_dev, G, R,
+                       hook->mask_dev, tol, kmax, S + ((K + kRing - 2) % kRing) * R);
+    MBL_HIP(hipGetLastError());
+    return MBL_OK;
+  };
   auto check = [&](int which) -> mbl_status {
     MBL_HIP(hipEventSynchronize(bw->ev[which]));
+    if (hook) {
+      std::vector<int> restart(R, 0);
+      const double* rhs = nullptr;
+      bool keep = true;
+      MBL_TRY(hook->on_snapshot(bw->h_state + which * R, snap_iter[which], issued + 1, restart,
+                                &rhs, keep));
+      bool any = false;
+      for (int r = 0; r < R; ++r) any = any || restart[r];
+      if (any) MBL_TRY(restart_lanes(restart, rhs));
+      if (!keep) done = true;
+      return MBL_OK;
+    }
     bool all = true;
     for (int r = 0; r < R; ++r) all = all && bw->h_state[which * R + r].done;
     if (all) done = true;
     return MBL_OK;
   };
+  if (hook && (!use_graph || !std::is_same<T, double>::value)) {
+    set_error("internal: the streaming form needs FP64 and captured graphs");
+    return MBL_ERR_ARG;
+  }
   if (kmax >= 1) {
     MBL_TRY(iteration(1, s));
     issued = 1;
   }
-  while (!done && issued < kmax) {
-    const int64_t k_end = std::min(kmax, issued + kChunkIters);
+  while (!done && (hook || issued < kmax)) {
+    const int64_t k_end = hook ? issued + kChunkIters : std::min(kmax, issued + kChunkIters);
     if (use_graph && k_end - issued == kChunkIters) {
       for (int64_t rep = 0; rep < kChunkIters / kGraphIters; ++rep)
         MBL_HIP(hipGraphLaunch(gx, s));
@@ -881,12 +1070,17 @@ static mbl_status bminres_core(mbl_basis_s* b, mbl_batch_s* bw, const BatchDev& 
     MBL_HIP(hipMemcpyAsync(bw->h_state + slot * R, S + ((issued - 1) % kRing) * R,
                            sizeof(BState) * R, hipMemcpyDeviceToHost, s));
     MBL_HIP(hipEventRecord(bw->ev[slot], s));
+    snap_iter[slot] = issued - 1;
     ++pending;
     if (pending == 2) {
       MBL_TRY(check(slot ^ 1));
       --pending;
     }
     slot ^= 1;
+  }
+  if (hook) {
+    MBL_HIP(hipStreamSynchronize(s));
+    return MBL_OK;
   }
   if (pending > 0) MBL_TRY(check(slot ^ 1));
   if (issued >= 1) MBL_TRY(finish(issued, s));
@@ -1245,6 +1439,438 @@ static mbl_status bsi_lanczos_run(mbl_basis_s* b, mbl_batch_s* bw, const double*
   if (!all_ok) {
     set_error("some batched eigenpairs did not converge");
     return MBL_WARN_NOCONV;
+  }
+  return MBL_OK;
+}
+
+// ---- streaming form ---------------------------------------------------------
+// Each lane of the batch runs its own realization through Alg. 1. The lanes
+// share the MINRES launches (one batched iteration serves every lane), but a
+// lane's solve ends on its own: the hook below takes that lane's Lanczos
+// step (w = x - beta_k v_{k-1}, alpha_k, two classical Gram-Schmidt passes,
+// beta_{k+1}, v_{k+1}, the eigenpairs of T_k and the stopping rule of the
+// lockstep form) and restarts its MINRES on v_{k+1} while the other lanes
+// iterate on. A lane whose realization has converged writes its Ritz pairs,
+// residuals and twist overlaps and takes the next realization. The lockstep
+// form instead launches, per Lanczos step, as many iterations as the
+// slowest lane needs.
+struct DevMem {
+  void* p = nullptr;
+  ~DevMem() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+static mbl_status dev_alloc(DevMem& m, size_t bytes) {
+  if (hipMalloc(&m.p, std::max<size_t>(bytes, 256)) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("device allocation failed (streaming batch)");
+    return MBL_ERR_NOMEM;
+  }
+  return MBL_OK;
+}
+
+mbl_status bstream_si_lanczos(mbl_basis b, mbl_batch bw, StreamProblem* P, int nprob, int nev,
+                              int mmax, double minres_tol, int64_t minres_kmax, double eig_tol,
+                              double gap_tol, int precond, hipStream_t s) {
+  const int R = bw->R, L = b->L;
+  const int64_t n = b->n, NR = n * R, vstride = NR;
+  if (nprob <= 0) return MBL_OK;
+  if (mmax < 1 || mmax > bw->mmax || nev < 1 || nev > bw->nevmax || nev > mmax) {
+    set_error("streaming batch: mmax or nev beyond the workspace");
+    return MBL_ERR_ARG;
+  }
+  const bool verbose = std::getenv("MBL_VERBOSE") != nullptr;
+  const int G = bgrid(b, R);
+  const int GC = std::max<int>(1, std::min<int64_t>(256, (n + 255) / 256));   // CGS groups
+  DevMem mask, part, kidx, part3, U, vtmp;
+  MBL_TRY(dev_alloc(mask, sizeof(int) * R));
+  MBL_TRY(dev_alloc(part, sizeof(double) * (size_t)G * R));
+  MBL_TRY(dev_alloc(kidx, sizeof(int) * R));
+  MBL_TRY(dev_alloc(part3, sizeof(double) * (size_t)GC * (mmax + 1) * R));
+  MBL_TRY(dev_alloc(U, sizeof(double) * (size_t)NR * nev));
+  MBL_TRY(dev_alloc(vtmp, sizeof(double) * (size_t)n));
+  double* T1 = bw->r64;   // v_k, then v_{k+1}, then the next right-hand sides
+  double* T2 = bw->e;     // v_{k-1}
+  double* Ub = static_cast<double*>(U.p);
+
+  struct Lane {
+    int prob = -1;          // realization, -1: idle
+    int k = 0;              // Lanczos vectors v_1 .. v_k in V blocks 0 .. k-1
+    bool solving = false;   // MINRES on v_k in flight
+    int64_t K0 = 1;         // iteration its solve started at
+    double beta_k = 0.0;
+    std::vector<double> al, be, theta, Y;
+    int64_t iters = 0;
+    int noconv = 0;
+  };
+  std::vector<Lane> lane(R);
+  std::vector<double> Hh((size_t)R * L, 0.0), C0(R, 0.0);
+  int next = 0, done_probs = 0;
+  const auto t0 = std::chrono::steady_clock::now();
+  auto secs = [&]() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  };
+
+  auto lane_shift = [&](int r, double shift) {
+    double sh = 0;
+    for (int j = 0; j < L; ++j) sh += Hh[(size_t)r * L + j];
+    C0[r] = 0.25 * L + 0.5 * sh - shift;
+  };
+  auto upload = [&]() -> mbl_status {
+    MBL_HIP(hipStreamSynchronize(s));   // staging buffer reuse
+    std::copy(Hh.begin(), Hh.end(), bw->h_stage);
+    std::copy(C0.begin(), C0.end(), bw->h_stage + (size_t)R * L);
+    MBL_HIP(hipMemcpyAsync(bw->h, bw->h_stage, sizeof(double) * R * L, hipMemcpyHostToDevice, s));
+    MBL_HIP(hipMemcpyAsync(bw->c0, bw->h_stage + (size_t)R * L, sizeof(double) * R,
+                           hipMemcpyHostToDevice, s));
+    MBL_HIP(hipStreamSynchronize(s));
+    bw->last_up.clear();   // the lockstep form's upload cache no longer holds
+    return MBL_OK;
+  };
+  auto put_kidx = [&](const std::vector<int>& kv) -> mbl_status {
+    MBL_HIP(hipStreamSynchronize(s));
+    MBL_HIP(hipMemcpyAsync(kidx.p, kv.data(), sizeof(int) * R, hipMemcpyHostToDevice, s));
+    MBL_HIP(hipStreamSynchronize(s));
+    return MBL_OK;
+  };
+  // lane r takes realization p: fields, shift, and V column (all blocks 0,
+  // block 0 the raw start vector; normalised by normalise_new)
+  auto assign = [&](int r, int p) -> mbl_status {
+    Lane& ln = lane[r];
+    ln = Lane();
+    ln.prob = p;
+    ln.k = 1;
+    std::copy(P[p].h, P[p].h + L, Hh.begin() + (size_t)r * L);
+    lane_shift(r, P[p].sigma);
+    MBL_HIP(launch_splitmix(n, P[p].seed, static_cast<double*>(vtmp.p), s));
+    hipLaunchKernelGGL(k_blane_reset, dim3(bflat_grid(n)), dim3(kWG), 0, s, n, R, r, bw->V,
+                       vstride, mmax + 1, static_cast<const double*>(vtmp.p));
+    MBL_HIP(hipGetLastError());
+    return MBL_OK;
+  };
+  auto normalise_new = [&](const std::vector<int>& fresh) -> mbl_status {
+    std::vector<double> nv(R), a(R, 1.0), zero(R, 0.0);
+    MBL_TRY(bdot_host(bw, n, bw->V, bw->V, nv.data(), s));
+    for (int r = 0; r < R; ++r) {
+      if (!fresh[r]) continue;
+      if (!(nv[r] > 0) || !std::isfinite(nv[r])) {
+        set_error("start vector has zero or non-finite norm");
+        return MBL_ERR_NUMERIC;
+      }
+      a[r] = 1.0 / std::sqrt(nv[r]);
+    }
+    return baxpby(bw, n, a, bw->V, zero, bw->V, s);
+  };
+
+  // finish the realizations of the lanes in fin: Ritz vectors of the pairs
+  // nearest sigma, normalised; explicit residuals; twist overlaps; outputs
+  auto finish = [&](const std::vector<int>& fin, std::vector<std::vector<int>>& sel)
+      -> mbl_status {
+    for (int r = 0; r < R; ++r) {   // the selected pairs in ascending eigenvalue
+      if (!fin[r]) continue;
+      const double sg = P[lane[r].prob].sigma;
+      const std::vector<double>& th = lane[r].theta;
+      std::sort(sel[r].begin(), sel[r].end(),
+                [&](int a, int c) { return sg + 1.0 / th[a] < sg + 1.0 / th[c]; });
+    }
+    int kmaxr = 1;
+    for (int r = 0; r < R; ++r)
+      if (fin[r]) kmaxr = std::max(kmaxr, (int)lane[r].al.size());
+    std::vector<double> Ys((size_t)R * kmaxr * nev, 0.0), lam((size_t)R * nev, 0.0);
+    for (int r = 0; r < R; ++r) {
+      if (!fin[r]) continue;
+      const Lane& ln = lane[r];
+      const int kr = (int)ln.al.size();
+      for (int t = 0; t < nev; ++t) {
+        lam[(size_t)r * nev + t] = P[ln.prob].sigma + 1.0 / ln.theta[sel[r][t]];
+        for (int c = 0; c < kr; ++c)
+          Ys[((size_t)r * kmaxr + c) * nev + t] = ln.Y[(size_t)sel[r][t] * kr + c];
+      }
+    }
+    MBL_HIP(hipStreamSynchronize(s));
+    MBL_HIP(hipMemcpyAsync(bw->ycoef, Ys.data(), sizeof(double) * Ys.size(),
+                           hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_britz, dim3(bflat_grid(NR), nev), dim3(kWG), 0, s, n, R, bw->V, vstride,
+                       kmaxr, bw->ycoef, nev, Ub, NR);
+    MBL_HIP(hipGetLastError());
+    std::vector<double> nn(R), invn(R), zero(R, 0.0), rn((size_t)R * nev), rr(R);
+    for (int t = 0; t < nev; ++t) {
+      double* u = Ub + (size_t)t * NR;
+      MBL_TRY(bdot_host(bw, n, u, u, nn.data(), s));
+      for (int r = 0; r < R; ++r) invn[r] = (fin[r] && nn[r] > 0) ? 1.0 / std::sqrt(nn[r]) : 0.0;
+      MBL_TRY(baxpby(bw, n, invn, u, zero, u, s));
+    }
+    // residuals ||H u - lambda u||: the finishing lanes' shifts set to lambda_t
+    for (int t = 0; t < nev; ++t) {
+      for (int r = 0; r < R; ++r)
+        if (fin[r]) lane_shift(r, lam[(size_t)r * nev + t]);
+      MBL_TRY(upload());
+      MBL_TRY(bapply_norms(b, bw, Ub + (size_t)t * NR, rr.data(), s));
+      for (int r = 0; r < R; ++r) rn[(size_t)r * nev + t] = rr[r];
+    }
+    std::vector<double> zz((size_t)R * nev * 2);
+    {
+      const mbl_status st = mbl_twist_expect_batched(b, bw, Ub, nev, zz.data(), s);
+      if (st != MBL_OK) return st;
+    }
+    for (int r = 0; r < R; ++r) {
+      if (!fin[r]) continue;
+      Lane& ln = lane[r];
+      StreamProblem& pr = P[ln.prob];
+      const double sg = pr.sigma;
+      // the pr.nev of the nev pairs nearest sigma, ascending
+      std::vector<int> o(nev);
+      std::iota(o.begin(), o.end(), 0);
+      std::stable_sort(o.begin(), o.end(), [&](int a, int c) {
+        return std::fabs(lam[(size_t)r * nev + a] - sg) < std::fabs(lam[(size_t)r * nev + c] - sg);
+      });
+      o.resize(pr.nev);
+      std::sort(o.begin(), o.end());
+      int nconv = 0;
+      double mx = 0.0;
+      for (int t = 0; t < pr.nev; ++t) {
+        const int src = o[t];
+        pr.evals[t] = lam[(size_t)r * nev + src];
+        const double res = rn[(size_t)r * nev + src];
+        if (pr.resid) pr.resid[t] = res;
+        if (pr.z) {
+          pr.z[2 * t] = zz[((size_t)r * nev + src) * 2];
+          pr.z[2 * t + 1] = zz[((size_t)r * nev + src) * 2 + 1];
+        }
+        hipLaunchKernelGGL(k_blane_get, dim3(bflat_grid(n)), dim3(kWG), 0, s, n, R, r,
+                           Ub + (size_t)src * NR, pr.evecs_dev + (size_t)t * n);
+        MBL_HIP(hipGetLastError());
+        mx = std::max(mx, res / pr.escale);
+        if (res <= eig_tol * pr.escale) ++nconv;
+      }
+      pr.steps = (int)ln.al.size();
+      pr.nconv = nconv;
+      pr.minres_iters = ln.iters;
+      pr.max_rel = mx;
+      if (pr.status == MBL_OK && nconv < pr.nev) pr.status = MBL_WARN_NOCONV;
+      ++done_probs;
+      if (verbose)
+        std::fprintf(stderr,
+                     "[mbl] stream L=%d: realization %d done (%d steps, %lld MINRES iterations), "
+                     "%d of %d (%.0f s)\n",
+                     L, ln.prob, pr.steps, (long long)ln.iters, done_probs, nprob, secs());
+      ln.prob = -1;
+      ln.solving = false;
+    }
+    MBL_HIP(hipStreamSynchronize(s));
+    return MBL_OK;
+  };
+
+  // the Lanczos step of the lanes in M (their solves x = (H - sigma)^{-1} v_k
+  // are final in bw->x); sets conv[r] for lanes that stop, with their pair
+  // selection in sel[r]
+  auto lanczos_step = [&](const std::vector<int>& M, std::vector<int>& stop,
+                          std::vector<std::vector<int>>& sel) -> mbl_status {
+    std::vector<int> k1(R, -1), k2(R, -1);
+    int kM = 1;
+    for (int r = 0; r < R; ++r) {
+      if (!M[r]) continue;
+      k1[r] = lane[r].k - 1;
+      k2[r] = lane[r].k >= 2 ? lane[r].k - 2 : -1;
+      kM = std::max(kM, lane[r].k);
+    }
+    MBL_TRY(put_kidx(k1));
+    hipLaunchKernelGGL(k_blane_gather, dim3(bflat_grid(NR)), dim3(kWG), 0, s, n, R, bw->V,
+                       vstride, static_cast<const int*>(kidx.p), T1);
+    MBL_TRY(put_kidx(k2));
+    hipLaunchKernelGGL(k_blane_gather, dim3(bflat_grid(NR)), dim3(kWG), 0, s, n, R, bw->V,
+                       vstride, static_cast<const int*>(kidx.p), T2);
+    MBL_HIP(hipGetLastError());
+    MBL_HIP(hipMemcpyAsync(bw->w, bw->x, sizeof(double) * NR, hipMemcpyDeviceToDevice, s));
+    std::vector<double> a(R, 0.0), one(R, 1.0), zero(R, 0.0), alpha(R), bb(R);
+    for (int r = 0; r < R; ++r)
+      if (M[r] && lane[r].k >= 2) a[r] = -lane[r].beta_k;
+    MBL_TRY(baxpby(bw, n, a, T2, one, bw->w, s));
+    MBL_TRY(bdot_host(bw, n, T1, bw->w, alpha.data(), s));
+    for (int r = 0; r < R; ++r) a[r] = M[r] ? -alpha[r] : 0.0;
+    MBL_TRY(baxpby(bw, n, a, T1, one, bw->w, s));
+    for (int pass = 0; pass < 2; ++pass) {   // CGS2 against v_1 .. v_k (zero blocks beyond)
+      hipLaunchKernelGGL(k_bmultidot, dim3(GC, (kM + 3) / 4), dim3(kWG), 0, s, n, R, bw->V,
+                         vstride, kM, bw->w, static_cast<double*>(part3.p));
+      MBL_HIP(hipGetLastError());
+      hipLaunchKernelGGL(k_breduce, dim3(kM * R), dim3(kWG), 0, s,
+                         static_cast<const double*>(part3.p), GC, kM * R, 1, bw->coef);
+      MBL_HIP(hipGetLastError());
+      hipLaunchKernelGGL(k_bcgs_update, dim3(bflat_grid(NR)), dim3(kWG), sizeof(double) * kM * R,
+                         s, n, R, bw->V, vstride, kM, bw->coef, bw->w);
+      MBL_HIP(hipGetLastError());
+    }
+    MBL_TRY(bdot_host(bw, n, bw->w, bw->w, bb.data(), s));
+    std::vector<double> invb(R, 0.0);
+    for (int r = 0; r < R; ++r) {
+      if (!M[r]) continue;
+      Lane& ln = lane[r];
+      const double bn = std::sqrt(bb[r]);
+      if (!std::isfinite(alpha[r]) || !std::isfinite(bn)) {
+        set_error("non-finite Lanczos coefficient (streaming batch)");
+        return MBL_ERR_NUMERIC;
+      }
+      ln.al.push_back(alpha[r]);
+      ln.be.push_back(bn);
+      const int k = ln.k;
+      ln.theta.assign(k, 0.0);
+      ln.Y.assign((size_t)k * k, 0.0);
+      if (tridiag_eig(k, ln.al.data(), ln.be.data(), ln.theta.data(), ln.Y.data()) != 0) {
+        set_error("tridiagonal eigensolver did not converge (streaming batch)");
+        return MBL_ERR_NUMERIC;
+      }
+      double tmax = 0;
+      for (double t : ln.theta) tmax = std::max(tmax, std::fabs(t));
+      invb[r] = (bn > 1e-14 * tmax) ? 1.0 / bn : 0.0;
+      ln.beta_k = bn;
+    }
+    // v_{k+1} = w / beta_{k+1} into T1 and V block k
+    MBL_TRY(baxpby(bw, n, invb, bw->w, zero, T1, s));
+    std::vector<int> kn(R, -1);
+    for (int r = 0; r < R; ++r)
+      if (M[r] && lane[r].k <= mmax && invb[r] != 0.0) kn[r] = lane[r].k;
+    MBL_TRY(put_kidx(kn));
+    hipLaunchKernelGGL(k_blane_scatter, dim3(bflat_grid(NR)), dim3(kWG), 0, s, n, R, T1, bw->V,
+                       vstride, static_cast<const int*>(kidx.p));
+    MBL_HIP(hipGetLastError());
+    std::vector<double> nav(R);
+    MBL_TRY(bapply_norms(b, bw, T1, nav.data(), s));
+    for (int r = 0; r < R; ++r) {
+      if (!M[r]) continue;
+      Lane& ln = lane[r];
+      const int kr = ln.k;
+      const bool broke = invb[r] == 0.0;
+      bool conv = false;
+      if (kr >= nev) {
+        std::vector<int> idx(kr);
+        std::iota(idx.begin(), idx.end(), 0);
+        std::stable_sort(idx.begin(), idx.end(), [&](int x1, int x2) {
+          return std::fabs(ln.theta[x1]) > std::fabs(ln.theta[x2]);
+        });
+        sel[r].assign(idx.begin(), idx.begin() + nev);
+        const double sg = P[ln.prob].sigma, es = P[ln.prob].escale;
+        conv = true;
+        for (int i : sel[r]) {
+          const double est = broke ? 0.0
+                                   : std::fabs(ln.be.back() * ln.Y[(size_t)i * kr + (kr - 1)] /
+                                               ln.theta[i]) * nav[r];
+          const double lam = sg + 1.0 / ln.theta[i];
+          double gap = INFINITY;
+          for (int jj = 0; jj < kr; ++jj)
+            if (jj != i) gap = std::min(gap, std::fabs(sg + 1.0 / ln.theta[jj] - lam));
+          bool ok = est <= eig_tol * es;
+          if (gap_tol > 0) ok = ok && est <= gap_tol * gap;
+          conv = conv && ok;
+        }
+      }
+      if (conv || broke || kr >= mmax) {
+        if ((int)sel[r].size() < nev) {
+          set_error("Krylov space became invariant before nev steps (streaming batch)");
+          return MBL_ERR_NUMERIC;
+        }
+        if (broke) P[ln.prob].status = MBL_WARN_BREAKDOWN;
+        stop[r] = 1;
+      } else {
+        ln.k = kr + 1;
+      }
+    }
+    return MBL_OK;
+  };
+
+  // start: every lane takes a realization (or idles), all V blocks zero
+  MBL_HIP(hipMemsetAsync(bw->V, 0, sizeof(double) * (size_t)NR * (mmax + 1), s));
+  std::vector<int> fresh(R, 0);
+  for (int r = 0; r < R && next < nprob; ++r) {
+    MBL_TRY(assign(r, next++));
+    fresh[r] = 1;
+  }
+  MBL_TRY(normalise_new(fresh));
+  MBL_TRY(upload());
+  std::vector<double> sc(R);
+  for (int r = 0; r < R; ++r) {
+    sc[r] = fresh[r] ? 1.0 : 0.0;
+    lane[r].solving = fresh[r] != 0;
+    lane[r].K0 = 1;
+  }
+  MBL_HIP(hipMemcpyAsync(bw->scale, sc.data(), sizeof(double) * R, hipMemcpyHostToDevice, s));
+
+  MinresHook hook;
+  hook.mask_dev = static_cast<int*>(mask.p);
+  hook.part_dev = static_cast<double*>(part.p);
+  double last_report = 0.0;
+  hook.on_snapshot = [&](const BState* st, int64_t iter, int64_t next_k, std::vector<int>& restart,
+                         const double** rhs, bool& keep_going) -> mbl_status {
+    std::vector<int> M(R, 0);
+    bool anyM = false;
+    for (int r = 0; r < R; ++r) {
+      Lane& ln = lane[r];
+      if (!ln.solving || iter < ln.K0 || !st[r].done) continue;
+      if (st[r].bad) {
+        set_error("batched MINRES met a non-finite value (streaming)");
+        return MBL_ERR_NUMERIC;
+      }
+      ln.iters += st[r].k;
+      if (st[r].k >= minres_kmax) ++ln.noconv;
+      M[r] = 1;
+      anyM = true;
+    }
+    if (anyM) {
+      std::vector<int> stop(R, 0);
+      std::vector<std::vector<int>> sel(R);
+      MBL_TRY(lanczos_step(M, stop, sel));
+      bool anystop = false;
+      for (int r = 0; r < R; ++r) anystop = anystop || stop[r];
+      std::vector<int> nw(R, 0);
+      if (anystop) {
+        MBL_TRY(finish(stop, sel));
+        bool anynew = false;
+        for (int r = 0; r < R; ++r)
+          if (stop[r] && next < nprob) {
+            MBL_TRY(assign(r, next++));
+            nw[r] = 1;
+            anynew = true;
+          }
+        if (anynew) MBL_TRY(normalise_new(nw));
+        MBL_TRY(upload());   // fields of new lanes (and shifts of finished ones)
+      }
+      // the right-hand sides v_k of every lane that starts a solve
+      std::vector<int> kv(R, -1);
+      for (int r = 0; r < R; ++r) {
+        if ((M[r] && !stop[r]) || nw[r]) {
+          restart[r] = 1;
+          kv[r] = lane[r].k - 1;
+          lane[r].solving = true;
+          lane[r].K0 = next_k;
+        } else if (M[r]) {
+          lane[r].solving = lane[r].prob >= 0;
+        }
+      }
+      MBL_TRY(put_kidx(kv));
+      hipLaunchKernelGGL(k_blane_gather, dim3(bflat_grid(NR)), dim3(kWG), 0, s, n, R, bw->V,
+                         vstride, static_cast<const int*>(kidx.p), T1);
+      MBL_HIP(hipGetLastError());
+      *rhs = T1;
+    }
+    bool any = false;
+    for (int r = 0; r < R; ++r) any = any || lane[r].solving;
+    keep_going = any;
+    if (verbose && secs() - last_report >= 30.0) {
+      last_report = secs();
+      int live = 0;
+      for (int r = 0; r < R; ++r) live += lane[r].solving;
+      std::fprintf(stderr, "[mbl] stream L=%d: %d of %d realizations done, %d lanes busy (%.0f s)\n",
+                   L, done_probs, nprob, live, secs());
+    }
+    return MBL_OK;
+  };
+  BatchDev Q{bw->h, bw->c0, R};
+  std::vector<BState> fin;
+  MBL_TRY(bminres_core<double>(b, bw, Q, precond, bw->V, bw->scale, bw->x, minres_tol,
+                               minres_kmax, s, fin, &hook));
+  if (done_probs != nprob) {
+    set_error("internal: streaming batch ended with realizations left");
+    return MBL_ERR_NUMERIC;
   }
   return MBL_OK;
 }

@@ -22,6 +22,8 @@ struct BState {
   double d_inv_beta, d_delta, d_eps, d_inv_gamma, d_tau;   // d/x update coefficients
   int64_t k;
   int32_t done, bad;
+  int32_t fresh;                // a restarted solve: the next Givens step carries this state
+  int32_t pad_;
 };
 
 struct BatchDev {
@@ -357,10 +359,16 @@ __device__ __forceinline__ double bsum_prefetched(const BPrefetch& f, int G, int
 // from the state after iteration k - 1, alpha_k and q_{k+1} . z_{k+1}, the
 // state after iteration k (beta_{k+1}, the Givens rotation, the d/x
 // coefficients of iteration k, phi_k, done). A done state is carried with a
-// zero step.
+// zero step. A fresh state (a solve restarted for one realization while the
+// others run on) is carried unchanged, as the state after the iteration
+// before its first one.
 __device__ __forceinline__ BState bgivens_step(const BState& si, double alpha, double qz,
                                                double tol, int64_t kmax) {
   BState so = si;
+  if (si.fresh) {
+    so.fresh = 0;
+    return so;
+  }
   if (si.done) {
     so.d_tau = 0.0;
     return so;

@@ -237,4 +237,31 @@ mbl_status minres_run(mbl_basis_s* b, const double* h_host, double sigma, const 
 // host symmetric tridiagonal eigensolver (symmetric QR with Wilkinson shifts)
 int tridiag_eig(int k, const double* alpha, const double* beta, double* evals, double* evecs);
 
+// One realization for the streaming batched SI-Lanczos (batched.hip): inputs,
+// then outputs.
+struct StreamProblem {
+  const double* h;      // L fields (host)
+  double sigma;         // shift
+  double escale;        // energy scale of the stopping rule (> 0)
+  int nev;              // pairs kept: the nev nearest sigma, ascending (<= the run's nev)
+  uint64_t seed;        // start vector: the SplitMix64 stream of this seed, normalised
+  double* evals;        // nev (host)
+  double* resid;        // nev explicit residuals (host) or null
+  double* z;            // 2 nev twist overlaps (host) or null
+  double* evecs_dev;    // n x nev column-major (device)
+  int steps = 0, nconv = 0;
+  int64_t minres_iters = 0;
+  double max_rel = 0.0;
+  mbl_status status = MBL_OK;
+};
+
+// Alg. 1 for many realizations of one L on the R lanes of a batch workspace,
+// each lane running its own Lanczos steps: when a lane's MINRES solve ends,
+// its Lanczos step is taken and its next solve starts while the other lanes
+// iterate on, and a lane whose realization has converged takes the next one.
+// FP64. The workspace's mmax and nevmax bound mmax and nev.
+mbl_status bstream_si_lanczos(mbl_basis b, mbl_batch w, StreamProblem* probs, int nprob, int nev,
+                              int mmax, double minres_tol, int64_t minres_kmax, double eig_tol,
+                              double gap_tol, int precond, hipStream_t s);
+
 }  // namespace mbl

@@ -40,6 +40,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <numeric>
@@ -1052,11 +1053,14 @@ static mbl_status campaign_small(mbl_problem* probs, const std::vector<int>& idx
   return MBL_OK;
 }
 
-// Problems with L > kWgMaxL: lockstep batches of one chain length (the
-// batched form), up to 32 realizations, padded to a power of two. A batch
-// launches, per Lanczos step, as many MINRES iterations as its slowest
-// realization needs, so each chain length's problems are ordered by disorder
-// strength first and a batch holds realizations of similar cost.
+double gershgorin_bound(const mbl_basis_s* b, const double* h);
+
+// Problems with L > kWgMaxL: the streaming batched form, one run per chain
+// length on up to 32 lanes. Each lane runs its own realization's Lanczos
+// steps and takes the next realization when its own has converged, so no
+// lane waits for the slowest solve of a step. The realizations of each chain
+// length are queued by disorder strength, weakest (most expensive) first, so
+// the long ones start early and the last lanes to drain hold short ones.
 static mbl_status campaign_large(mbl_problem* probs, const std::vector<int>& idx,
                                  const std::vector<int>& mm, double minres_tol,
                                  int64_t minres_kmax, double eig_tol, double gap_tol,
@@ -1076,90 +1080,56 @@ static mbl_status campaign_large(mbl_problem* probs, const std::vector<int>& idx
       mbl_basis b;
       ~BG() { mbl_basis_free(b); }
     } bg{b};
-    const int64_t n = b->n;
-    for (size_t off = 0; off < all.size();) {
-      int R = 2;
-      while (R < 32 && R < (int)(all.size() - off)) R *= 2;
-      const int take = std::min<int>(R, (int)(all.size() - off));
-      int nev = 1, mmax = 1;
-      for (int q = 0; q < take; ++q) {
-        nev = std::max(nev, probs[all[off + q]].nev);
-        mmax = std::max(mmax, mm[all[off + q]]);
+    int R = 2;
+    while (R < 32 && R < (int)all.size()) R *= 2;
+    int nev = 1, mmax = 1;
+    for (int i : all) {
+      nev = std::max(nev, probs[i].nev);
+      mmax = std::max(mmax, mm[i]);
+    }
+    mbl_batch bt = nullptr;
+    mbl_status st = mbl_batch_create(b, R, mmax, nev, &bt);
+    while (st < 0 && R > 2) {   // too wide for this L: halve
+      R /= 2;
+      st = mbl_batch_create(b, R, mmax, nev, &bt);
+    }
+    MBL_TRY(st);
+    struct BTG {
+      mbl_batch b;
+      ~BTG() { mbl_batch_free(b); }
+    } btg{bt};
+    std::vector<StreamProblem> sp(all.size());
+    for (size_t q = 0; q < all.size(); ++q) {
+      mbl_problem& pr = probs[all[q]];
+      double emin = 0, emax = 0, sg = pr.sigma, es = pr.escale;
+      if (std::isnan(sg)) {
+        MBL_TRY(mbl_sigma_midpoint(b, pr.h_host, 1e-12, 0, &emin, &emax, &sg, s));
+        if (!(es > 0)) es = std::max(std::fabs(emin), std::fabs(emax));
+      } else if (!(es > 0)) {
+        es = gershgorin_bound(b, pr.h_host);
       }
-      mbl_batch bt = nullptr;
-      mbl_status st = mbl_batch_create(b, R, mmax, nev, &bt);
-      while (st < 0 && R > 2) {   // too wide for this L: halve
-        R /= 2;
-        st = mbl_batch_create(b, R, mmax, nev, &bt);
-      }
-      MBL_TRY(st);
-      struct BTG {
-        mbl_batch b;
-        ~BTG() { mbl_batch_free(b); }
-      } btg{bt};
-      const int used = std::min<int>(R, (int)(all.size() - off));
-      std::vector<double> h((size_t)R * L), sig(R), esc(R);
-      for (int r = 0; r < R; ++r) {
-        const mbl_problem& pr = probs[all[off + std::min(r, used - 1)]];
-        std::copy(pr.h_host, pr.h_host + L, h.begin() + (size_t)r * L);
-        double emin = 0, emax = 0, sg = pr.sigma;
-        if (std::isnan(sg)) {
-          MBL_TRY(mbl_sigma_midpoint(b, pr.h_host, 1e-12, 0, &emin, &emax, &sg, s));
-          esc[r] = pr.escale > 0 ? pr.escale : std::max(std::fabs(emin), std::fabs(emax));
-        } else {
-          esc[r] = pr.escale;   // <= 0: the batched form's Gershgorin bound
-        }
-        sig[r] = sg;
-      }
-      DevBuf U;
-      MBL_TRY(alloc_dev(U, sizeof(double) * (size_t)n * R * nev));
-      std::vector<double> ev((size_t)R * nev), rs((size_t)R * nev), zz((size_t)R * nev * 2);
-      std::vector<mbl_si_info> inf(R);
-      const mbl_status sb = mbl_si_lanczos_batched(
-          b, bt, h.data(), sig.data(), nev, mmax, minres_tol, minres_kmax, eig_tol, gap_tol,
-          esc.data(), nullptr, seed, MBL_FP64, precond, ev.data(), static_cast<double*>(U.p),
-          rs.data(), inf.data(), s);
-      if (sb < 0) return sb;
-      MBL_TRY(mbl_twist_expect_batched(b, bt, static_cast<const double*>(U.p), nev, zz.data(), s));
-      for (int r = 0; r < used; ++r) {
-        mbl_problem& pr = probs[all[off + r]];
-        // the batch ran with the widest nev of its problems: keep the pr.nev
-        // pairs nearest sigma, in ascending order
-        std::vector<int> o(nev);
-        std::iota(o.begin(), o.end(), 0);
-        std::stable_sort(o.begin(), o.end(), [&](int a, int c) {
-          return std::fabs(ev[(size_t)r * nev + a] - sig[r]) < std::fabs(ev[(size_t)r * nev + c] - sig[r]);
-        });
-        o.resize(pr.nev);
-        std::sort(o.begin(), o.end());
-        int nconv = 0;
-        double mx = 0.0;
-        const double es = esc[r] > 0 ? esc[r] : 1.0;
-        for (int t = 0; t < pr.nev; ++t) {
-          const int src = o[t];
-          pr.evals_host[t] = ev[(size_t)r * nev + src];
-          const double res = rs[(size_t)r * nev + src];
-          if (pr.resid_host) pr.resid_host[t] = res;
-          if (pr.z_host) {
-            pr.z_host[2 * t] = zz[((size_t)r * nev + src) * 2];
-            pr.z_host[2 * t + 1] = zz[((size_t)r * nev + src) * 2 + 1];
-          }
-          hipLaunchKernelGGL(k_deinterleave, dim3(256), dim3(kWG), 0, s, n, R, 1, r,
-                             static_cast<const double*>(U.p) + (size_t)src * n * R,
-                             pr.evecs_dev + (size_t)t * n);
-          MBL_HIP(hipGetLastError());
-          mx = std::max(mx, res / es);
-          if (res <= eig_tol * es) ++nconv;
-        }
-        pr.sigma_out = sig[r];
-        pr.info.steps = inf[r].steps;
-        pr.info.nconv = nconv;
-        pr.info.minres_iters = inf[r].minres_iters;
-        pr.info.max_rel_resid = mx;
-        pr.status = nconv == pr.nev ? MBL_OK : MBL_WARN_NOCONV;
-      }
-      MBL_HIP(hipStreamSynchronize(s));
-      off += used;
+      StreamProblem& p = sp[q];
+      p.h = pr.h_host;
+      p.sigma = sg;
+      p.escale = es;
+      p.nev = pr.nev;
+      p.seed = seed + 0x9E3779B97F4A7C15ull * (uint64_t)(all[q] + 1);
+      p.evals = pr.evals_host;
+      p.resid = pr.resid_host;
+      p.z = pr.z_host;
+      p.evecs_dev = pr.evecs_dev;
+      pr.sigma_out = sg;
+    }
+    MBL_TRY(bstream_si_lanczos(b, bt, sp.data(), (int)sp.size(), nev, mmax, minres_tol,
+                               minres_kmax, eig_tol, gap_tol, precond, s));
+    for (size_t q = 0; q < all.size(); ++q) {
+      mbl_problem& pr = probs[all[q]];
+      const StreamProblem& p = sp[q];
+      pr.info.steps = p.steps;
+      pr.info.nconv = p.nconv;
+      pr.info.minres_iters = p.minres_iters;
+      pr.info.max_rel_resid = p.max_rel;
+      pr.status = p.status;
     }
   }
   return MBL_OK;
@@ -1180,6 +1150,14 @@ extern "C" mbl_status mbl_si_lanczos_problems(mbl_problem* probs, int nprob, int
   MBL_ARG(std::isfinite(gap_tol), "gap_tol must be finite");
   MBL_ARG(precond >= 0 && precond <= 2, "unknown preconditioner");
   MBL_ARG(mmax == 0 || (mmax >= 1 && mmax <= kWgMaxM), "mmax must be 0 or in [1, 128]");
+  // the longest chain of the persistent launch: 16, or MBL_PERSISTENT_MAX_L
+  // (even, 4..16) to send shorter chains to the streaming batches as well
+  int max_small = kWgMaxL;
+  if (const char* e = std::getenv("MBL_PERSISTENT_MAX_L")) {
+    const int v = std::atoi(e);
+    MBL_ARG(v >= 4 && v <= kWgMaxL && v % 2 == 0, "MBL_PERSISTENT_MAX_L must be even in [4, 16]");
+    max_small = v;
+  }
   std::vector<int> small, large, mm(nprob);
   for (int i = 0; i < nprob; ++i) {
     const mbl_problem& pr = probs[i];
@@ -1193,7 +1171,7 @@ extern "C" mbl_status mbl_si_lanczos_problems(mbl_problem* probs, int nprob, int
     m = (int)std::min<uint64_t>((uint64_t)m, n);
     MBL_ARG(m >= pr.nev, "mmax must be >= nev");
     mm[i] = m;
-    (pr.L <= kWgMaxL ? small : large).push_back(i);
+    (pr.L <= max_small ? small : large).push_back(i);
   }
   for (int i = 0; i < nprob; ++i) {
     probs[i].status = MBL_OK;

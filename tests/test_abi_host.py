@@ -86,6 +86,24 @@ def test_tridiag_eig_clustered_and_split():
     assert np.allclose(T @ V, V * w[None, :], atol=1e-11)
 
 
+@pytest.mark.parametrize("scale", [1e-150, 1.0, 1e150])
+def test_tridiag_eig_graded_and_scaled(mbl, scale):
+    """A graded matrix (entries falling by 10^-0.5 per row) and W21+ at
+    scales far from 1: eigenvalues to 1e-12 of the largest, eigenvectors
+    orthonormal and with residuals to 1e-11 relative."""
+    k = 40
+    a = scale * 10.0 ** (-0.5 * np.arange(k))
+    b = scale * 0.3 * 10.0 ** (-0.5 * np.arange(k - 1) - 0.25)
+    for aa, bb in ((a, b), (scale * np.abs(np.arange(-10, 11)).astype(float), scale * np.ones(20))):
+        w, V = mbl.tridiag_eig(aa, bb)
+        T = np.diag(aa) + np.diag(bb, 1) + np.diag(bb, -1)
+        wr = np.linalg.eigvalsh(T)
+        top = np.abs(wr).max()
+        assert np.all(np.abs(w - wr) <= 1e-12 * top)
+        assert np.abs(T @ V - V * w[None, :]).max() <= 1e-11 * top
+        assert np.allclose(V.T @ V, np.eye(len(aa)), atol=1e-12)
+
+
 def test_single_hip_runtime_in_process():
     """The binding loads torch's HIP runtime first, so libmbl.so resolves its
     libamdhip64.so.7 dependency to it: one runtime serves torch's streams and

@@ -179,13 +179,23 @@ def test_minres_parity(gpu, torch, L, h, seed, kind):
     assert np.linalg.norm(host(x) - xd) / np.linalg.norm(xd) <= 1e-8
     assert info.phi < 1e-12
     if L <= 12:
+        # The count at the threshold depends on rounding: the oracle's own
+        # count moves when its product is perturbed by 2e-16 relative noise
+        # (by up to 7 % at L = 12, h = 2). The GPU sums in another order, so
+        # its count must lie in the oracle's rounding ensemble widened by the
+        # ensemble's spread (+3).
         A = precond.shifted(H, sigma)
         m = precond.preconditioner_diagonal(H, sigma, kind)
-        _, k_ref, _ = minres.minres(lambda v: A @ v, np.zeros_like(bvec), bvec, 1.0 / m,
-                                    10**6, 1e-12)
-        # same recurrence; partial sums are reduced over a different grid than
-        # the oracle's dot products, so the count at the threshold may drift a little
-        assert abs(info.iters - k_ref) <= 0.05 * k_ref + 5
+        ks = []
+        for j in range(6):
+            rng = np.random.default_rng(1000 + j)
+            op = (lambda v: A @ v) if j == 0 else \
+                (lambda v, g=rng: (A @ v) * (1 + 2e-16 * g.standard_normal(v.shape[0])))
+            _, k_ref, _ = minres.minres(op, np.zeros_like(bvec), bvec, 1.0 / m, 10**6, 1e-12)
+            ks.append(k_ref)
+        lo, hi = min(ks), max(ks)
+        say(f"  GPU iterations {info.iters}, oracle rounding ensemble {ks}")
+        assert lo - (hi - lo) - 3 <= info.iters <= hi + (hi - lo) + 3
 
 
 def test_minres_nonzero_start_and_kmax_warning(gpu, torch):

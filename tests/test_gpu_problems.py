@@ -1,8 +1,9 @@
 """Many realizations of uneven chain length in one call
 (mbl_si_lanczos_problems): the persistent per-workgroup solver (L <= 16)
 against the oracle's dense eigenpairs, the stored L = 16 sparse reference and
-the single-realization path; the lockstep batches the call runs for L >= 18
-against the stored L = 18 sparse reference, in a call that mixes both.
+the single-realization path; the streaming batches the call runs for L >= 18
+against the stored L = 18 sparse reference, in a call that mixes both, and at
+small L (40 realizations on 32 lanes) against the dense eigenpairs.
 
 Bars as for mbl_si_lanczos: sigma and the extremes 1e-10 relative; eigenvalues
 |E - E_ref| / max(|E_ref|, 1) <= 1e-10; 1 - |<u, u_ref>| <= 1e-10; explicit
@@ -119,10 +120,10 @@ def test_L16_against_stored_sparse_reference(gpu):
         _check_stored(g, r)
 
 
-def test_L18_lockstep_route_in_a_mixed_call(gpu):
+def test_L18_streaming_route_in_a_mixed_call(gpu):
     """L = 18 (stored reference, sigma computed by the call) beside an L = 12
     realization of the persistent launch and a second L = 18 realization of
-    other fields that shares the lockstep batch."""
+    other fields that shares the streaming batch."""
     g = json.load(open(os.path.join(HERE, "golden", "si_L18_h3_seed0.json")))
     f = np.array(g["fields"])
     probs = [dict(L=12, h=disorder_fields(12, 3.0, 41), nev=4),
@@ -140,6 +141,26 @@ def test_L18_lockstep_route_in_a_mixed_call(gpu):
     escale = max(abs(lo), abs(hi))
     assert abs(r.sigma - 0.5 * (lo + hi)) <= 1e-10 * escale
     assert np.all(rr <= 1e-10 * escale)
+
+
+def test_streaming_lanes_take_new_realizations(gpu, monkeypatch):
+    """The streaming batched form at small L (MBL_PERSISTENT_MAX_L=10 sends
+    L = 12 and 14 there): 40 realizations of L = 12 on 32 lanes (8 lanes take
+    a second realization when their first has converged) and 3 of L = 14 with
+    another nev, each against the oracle's dense eigenpairs."""
+    monkeypatch.setenv("MBL_PERSISTENT_MAX_L", "10")
+    probs = []
+    for k in range(40):
+        probs.append(dict(L=12, h=disorder_fields(12, (1.0, 2.0, 3.0, 4.0)[k % 4], 300 + k),
+                          nev=4 if k % 3 else 6))
+    for k in range(3):
+        probs.append(dict(L=14, h=disorder_fields(14, 3.0, 400 + k), nev=5))
+    st, res = gpu.si_lanczos_problems(probs, seed=21, minres_kmax=400_000)
+    assert st == 0
+    for p, r in zip(probs, res):
+        _check_dense(p["L"], p["h"], r, p["nev"])
+    say(f"  streaming: {len(res)} realizations, steps {min(r.steps for r in res)}..."
+        f"{max(r.steps for r in res)}, t={res[0].seconds:.1f}s")
 
 
 def test_problem_array_rejects_bad_arguments(gpu):
