@@ -62,7 +62,7 @@ enum {
 /* Diagonal preconditioner M = C C^dagger (Sec. II). */
 enum {
   MBL_PRECOND_ROW = 0,     /* M = diag(r_i), r_i = 2-norm of row i of H - sigma I
-                              (Eq. (rownorm_preconditioner)) */
+                              (the row-norm preconditioner of Sec. II) */
   MBL_PRECOND_JACOBI = 1,  /* M = diag(|a_ii - sigma|); an element equal to 0 is
                               an argument error at solve time (MBL_ERR_NUMERIC) */
   MBL_PRECOND_ID = 2       /* M = I */
@@ -112,7 +112,7 @@ mbl_status mbl_apply_H_f32(mbl_basis b, const double* h_host, double sigma,
                            const float* x_dev, float* y_dev, void* stream);
 
 /* ---- q = M^{-1} z with the chosen diagonal preconditioner (Sec. II,
- * Eq. (rownorm_preconditioner)). z_dev, q_dev: n doubles (may alias). Async. */
+ * the row-norm preconditioner of Sec. II). z_dev, q_dev: n doubles (may alias). Async. */
 mbl_status mbl_precond_apply(mbl_basis b, const double* h_host, double sigma, int precond,
                              const double* z_dev, double* q_dev, void* stream);
 

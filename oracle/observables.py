@@ -9,7 +9,7 @@
 * ``spacing_ratios``: r_k = min(delta_k, delta_{k-1}) / max(delta_k,
   delta_{k-1}) with delta_k = E_{k+1} - E_k over the sorted eigenvalues.
 * ``rmt_entropy``: the random-matrix estimate of S quoted in Sec. IV,
-  Eq. (ee_random), as a reference curve (not a pin).
+  the random-state entropy of Sec. IV B, as a reference curve (not a pin).
 
 Readings where the paper is silent:
 * the logarithm is natural (the reference values use ln 2);
@@ -65,5 +65,5 @@ def mean_spacing_ratio(E: np.ndarray) -> float:
 
 
 def rmt_entropy(L: int) -> float:
-    """Eq. (ee_random): (ln 2 / 2) L + (1/2) ln(1/2) - 1/4."""
+    """The random-state entropy of Sec. IV B: (ln 2 / 2) L + (1/2) ln(1/2) - 1/4."""
     return 0.5 * np.log(2.0) * L + 0.5 * np.log(0.5) - 0.25

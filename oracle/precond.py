@@ -2,7 +2,7 @@
 
 * identity ("id", no preconditioner);
 * Jacobi: M = diag(|a_ii - sigma|), assumes a_ii != sigma;
-* row norm (Eq. (rownorm_preconditioner)): M = diag(r_i) with r_i the
+* row norm (the row-norm preconditioner of Sec. II): M = diag(r_i) with r_i the
   2-norm of row i of A - sigma I.
 
 The row norms are taken straight from the stored sparse rows, as defined.

@@ -12,7 +12,7 @@
   spectral midpoint), then per realization the mean level-spacing ratio,
   the mean half-chain entanglement entropy and the mean |z|^2 over its
   eigenstates; the row reports their mean and standard deviation over
-  realizations, next to the GOE and Poisson ratios and Eq. (ee_random), and
+  realizations, next to the GOE and Poisson ratios and the random-state entropy of Sec. IV B, and
   the per-realization values (with sigma and the eigenvalues).
 * ``eig``: one full shift-invert Lanczos run (sigma at the spectral midpoint,
   the nev pairs nearest it, MINRES tol 1e-12, eig_tol 1e-10), its time per

@@ -88,7 +88,7 @@ def test_entropy_closed_forms(gpu, torch, L):
 def test_entropy_of_eigenvectors_L14(gpu, torch):
     """Mid-spectrum eigenvectors from the library's shift-invert Lanczos:
     the entropies equal the oracle's on the same vectors, and at h = 0.5
-    (ergodic side) their mean is within 0.5 of Eq. (ee_random)."""
+    (ergodic side) their mean is within 0.5 of the random-state entropy of Sec. IV B."""
     L = 14
     say("entropy of SI-Lanczos eigenvectors L=14")
     b = gpu.Basis(L)

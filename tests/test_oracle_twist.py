@@ -69,7 +69,7 @@ def test_twist_energy_identity_and_bound(L):
 
 
 def test_gaussian_mean_abs_z2_is_2_over_n():
-    """Eq. (twist_thermal_gaussian): mean |z|^2 = 2/n for Gaussian c_alpha."""
+    """The Gaussian-state value of Sec. III (App. B): mean |z|^2 = 2/n for Gaussian c_alpha."""
     L = 10
     n = math.comb(L, L // 2)
     rng = np.random.default_rng(123)
@@ -104,7 +104,7 @@ def _perturbative_check(L, hs):
 
 
 def test_localized_perturbative_bound():
-    """Eq. (twist_perturbation_bound), App. C: the bound holds up to O(J^3), so
+    """The perturbative bound of Sec. III (App. C): the bound holds up to O(J^3), so
     the relative excess and the error of the second-order expression shrink
     like J/h as the disorder grows."""
     p1, b1 = _perturbative_check(8, 400.0)
