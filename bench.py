@@ -173,9 +173,10 @@ def eig_leg(mbl, torch, L, nev, R, batched_mixed=False):
     """Seconds per converged eigenpair (explicit FP64 residual <= 1e-10 escale)
     of the whole path (sigma, SI-Lanczos with MINRES, Ritz vectors, residual
     checks, twist) at chain length L: one realization per call in FP64 and
-    with FP32-inner MINRES, and R realizations in lockstep in FP64 (the
-    lockstep FP32-inner run only with batched_mixed). Every call is timed
-    whole, with sigma; nothing is projected."""
+    with FP32-inner MINRES, R realizations in lockstep in FP64 (the lockstep
+    FP32-inner run only with batched_mixed), and the same R realizations in
+    one problem-array call. Every call is timed whole, with sigma; nothing is
+    projected."""
     from workloads import disorder_fields
     from paper_2203_09732_amd import tune
     h = 3.0
@@ -222,9 +223,11 @@ def eig_leg(mbl, torch, L, nev, R, batched_mixed=False):
                                        "r_mean": round(mbl.spacing_ratio(res.evals)[0], 6)}
         if prec != "fp64" and not batched_mixed:
             continue
-        bb = mbl.Basis(L, tune.best_lo_bits(L, R, "fp64" if prec == "fp64" else "fp32"))
+        tp = "fp64" if prec == "fp64" else "fp32"
+        bb = mbl.Basis(L, tune.best_lo_bits(L, R, tp))
         mmax = min(bb.n, 3 * nev + 40)
         bt = mbl.Batch(bb, R, mmax=mmax, nevmax=nev)
+        tune.apply_schedule(bt, L, R, tp)
         torch.cuda.synchronize()
         t = time.perf_counter()
         sig, esc = [], []
@@ -243,6 +246,21 @@ def eig_leg(mbl, torch, L, nev, R, batched_mixed=False):
                                   "realizations": R, "seconds": round(dt, 3),
                                   "steps_max": int(resb.steps.max()),
                                   "minres_iters": int(resb.minres_iters)}
+    # the same R realizations through the problem-array call: the persistent
+    # launch (L <= 16) or the streaming lanes (L >= 18), sigma included
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    st, resp = mbl.si_lanczos_problems([dict(L=L, h=f, nev=nev) for f in fields], seed=7)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t
+    nconv = int(sum(r.nconv for r in resp))
+    progress(f"eig leg L={L} problem array ({R} realizations): {dt:.1f} s, {nconv} pairs")
+    out["problems_fp64"] = {"value": round(dt / max(nconv, 1), 4), "nconv": nconv,
+                            "realizations": R, "seconds": round(dt, 3),
+                            "form": "persistent" if L <= 16 else "streaming",
+                            "steps_max": int(max(r.steps for r in resp)),
+                            "minres_iters": int(sum(r.minres_iters for r in resp)),
+                            "max_rel_resid": float(max(r.max_rel_resid for r in resp))}
     out["unit"] = "s per converged eigenpair"
     return out
 
@@ -388,6 +406,7 @@ def main():
     YS = [torch.empty_like(XS[0]) for _ in range(NPAIRS)]
     X, Y = XS[0], YS[0]
     batch = mbl.Batch(basis, R)
+    tune.apply_schedule(batch, L, R, "fp64")
     stream = torch.cuda.current_stream()
     counter = [0]
 

@@ -284,6 +284,14 @@ typedef struct mbl_batch_s* mbl_batch;
 mbl_status mbl_batch_create(mbl_basis b, int R, int mmax, int nevmax, mbl_batch* out);
 void mbl_batch_free(mbl_batch w);
 mbl_status mbl_batch_bytes(mbl_batch w, int64_t* bytes);
+/* Launch schedule of a batch workspace's kernels (a tuning knob; results do
+ * not depend on it beyond the order of the partial sums): grid = workgroups
+ * of the row kernels (0: one per compute unit; else a multiple of 8 up to
+ * 512), graph_iters = MINRES iterations per captured graph (0 = 16; 8, 16 or
+ * 32), dx_group = MINRES iterations per d/x pass (0 = 4; 1, 2 or 4).
+ * MBL_ERR_ARG on other values. Drops the workspace's captured graphs when the
+ * schedule changes. */
+mbl_status mbl_batch_set_schedule(mbl_batch w, int grid, int graph_iters, int dx_group);
 /* y_r = (H_r - sigma_r) x_r for every r (Eq. (1)); interleaved x, y. Async. */
 mbl_status mbl_apply_H_batched(mbl_basis b, mbl_batch w, const double* h_host,
                                const double* sigma_host, const double* x_dev, double* y_dev,

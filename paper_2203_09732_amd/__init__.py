@@ -418,6 +418,7 @@ def tridiag_eig(alpha, beta):
 _sig("mbl_batch_create", _i32, [_vp, C.c_int, C.c_int, C.c_int, C.POINTER(_vp)])
 _sig("mbl_batch_free", None, [_vp])
 _sig("mbl_batch_bytes", _i32, [_vp, C.POINTER(C.c_int64)])
+_sig("mbl_batch_set_schedule", _i32, [_vp, C.c_int, C.c_int, C.c_int])
 _sig("mbl_apply_H_batched", _i32, [_vp, _vp, _dp, _dp, _vp, _vp, _vp])
 _sig("mbl_apply_H_batched_f32", _i32, [_vp, _vp, _dp, _dp, _vp, _vp, _vp])
 _sig("mbl_minres_solve_batched", _i32, [_vp, _vp, _dp, _dp, _vp, _vp, _d, _i64, C.c_int, C.c_int,
@@ -448,6 +449,13 @@ class Batch:
     @property
     def handle(self):
         return self._h
+
+    def set_schedule(self, grid: int = 0, graph_iters: int = 0, dx_group: int = 0):
+        """Launch schedule of the batched kernels (mbl_batch_set_schedule);
+        0 keeps the library's default for that knob."""
+        _check(lib.mbl_batch_set_schedule(self._h, int(grid), int(graph_iters), int(dx_group)),
+               "mbl_batch_set_schedule", warn_ok=False)
+        self.schedule = (int(grid), int(graph_iters), int(dx_group))
 
     def __del__(self):
         if getattr(self, "_h", None) and lib is not None:

@@ -122,6 +122,7 @@ def _run_lockstep(todo, nev, results_path, precision, minres_tol, eig_tol, gap_t
             mmax = min(basis.n, 3 * nev + 40)
             try:
                 batch = Batch(basis, R, mmax=mmax, nevmax=nev)
+                tune.apply_schedule(batch, L, R, precision)
                 break
             except Exception:
                 if R == 2:

@@ -435,7 +435,7 @@ __global__ __launch_bounds__(kBWG) void k_bgivens_last(BGivens gv, int R) {
 // ring and the coefficients from the ring of states, and stores only the last
 // two d's and x. Iterations in which a realization was already done are
 // skipped for it.
-constexpr int kDxGroup = 4;
+constexpr int kDxGroup = 4;   // the longest d/x pass (the schedule may use 1 or 2)
 constexpr int kRing = 8;   // q vectors and iteration states kept; a divisor of the graph length
 
 template <typename T>
@@ -714,6 +714,9 @@ struct mbl_batch_s {
   int64_t graph_kmax[2][3] = {{0, 0, 0}, {0, 0, 0}};
   void* graph_x[2][3] = {{nullptr, nullptr, nullptr}, {nullptr, nullptr, nullptr}};
   int graph_mode = -1;              // -1: unset (env), 0: eager launches, 1: graphs
+  // launch schedule (mbl_batch_set_schedule): row-kernel workgroups (0: one
+  // per CU), MINRES iterations per captured graph, iterations per d/x pass
+  int sched_grid = 0, sched_graph = 16, sched_dx = 4;
   hipStream_t cap = nullptr;        // capture stream (the caller's may be the null stream)
 };
 
@@ -739,7 +742,8 @@ static int device_cus(int device) {
   return cached[device];
 }
 
-static int bgrid(const mbl_basis_s* b, int R) {
+static int bgrid(const mbl_basis_s* b, int R, int grid = 0) {
+  if (grid > 0) return grid;   // a tuned schedule (a multiple of 8, <= kBGrid)
   const int64_t wave_steps = (int64_t)b->nchunks * std::max(1, R / 2);
   int64_t g = (wave_steps + (kBWG / 64) - 1) / (kBWG / 64);
   g = std::max<int64_t>(1, std::min<int64_t>({g, kBGrid, device_cus(b->device)}));
@@ -769,7 +773,7 @@ template <typename T, int MODE, bool GUARD>
 static mbl_status launch_bapply(const mbl_basis_s* b, const BatchDev& Q, const BGivens& gv,
                                 const T* x, T* y, double* partials, hipStream_t s) {
   const size_t lds = blds_bytes(Q.R, b->L, b->nlo);
-  const dim3 g(bgrid(b, Q.R)), blk(kBWG);
+  const dim3 g(bgrid(b, Q.R, Q.grid)), blk(kBWG);
   const DevBasis B = b->dev();
 #define MBL_CASE(LL, NN)                                                                    \
   case LL * 64 + NN:                                                                       \
@@ -786,7 +790,7 @@ static mbl_status launch_bresidual(const mbl_basis_s* b, const BatchDev& Q, int 
                                    const double* rhs, const double* x, double* res,
                                    double* partials, hipStream_t s) {
   const size_t lds = blds_bytes(Q.R, b->L, b->nlo);
-  const dim3 g(bgrid(b, Q.R)), blk(kBWG);
+  const dim3 g(bgrid(b, Q.R, Q.grid)), blk(kBWG);
   const DevBasis B = b->dev();
 #define MBL_CASE(LL, NN)                                                                       \
   case LL * 64 + NN:                                                                          \
@@ -804,7 +808,7 @@ static mbl_status launch_binit(const mbl_basis_s* b, const BatchDev& Q, int kind
                                const double* src, const double* scale, T* z0, T* z1, T* q1, T* d0,
                                T* d1, T* x, double* partials, hipStream_t s) {
   const size_t lds = blds_bytes(Q.R, b->L, b->nlo);
-  const dim3 g(bgrid(b, Q.R)), blk(kBWG);
+  const dim3 g(bgrid(b, Q.R, Q.grid)), blk(kBWG);
   const DevBasis B = b->dev();
 #define MBL_CASE(LL, NN)                                                                        \
   case LL * 64 + NN:                                                                           \
@@ -822,7 +826,7 @@ static mbl_status launch_bzq(const mbl_basis_s* b, const BatchDev& Q, int kind, 
                              const double* part1, double* alpha_out, const T* p, const T* zk,
                              T* zkm1, T* qn, double* partials, hipStream_t s) {
   const size_t lds = blds_bytes(Q.R, b->L, b->nlo);
-  const dim3 g(bgrid(b, Q.R)), blk(kBWG);
+  const dim3 g(bgrid(b, Q.R, Q.grid)), blk(kBWG);
   const DevBasis B = b->dev();
 #define MBL_CASE(LL, NN)                                                                        \
   case LL * 64 + NN:                                                                           \
@@ -906,7 +910,8 @@ static mbl_status bminres_core(mbl_basis_s* b, mbl_batch_s* bw, const BatchDev& 
   for (int i = 0; i < kRing; ++i) qr.q[i] = Qv[i] = (T*)bw->q[i];
   T* D[2] = {(T*)bw->d[0], (T*)bw->d[1]};
   T* P = (T*)bw->p;
-  const int G = bgrid(b, R);
+  const int G = bgrid(b, R, Q.grid);
+  const int dxg = bw->sched_dx;   // iterations per d/x pass (1, 2 or 4)
   BState* S = bw->S;
   // z_0 in Z[0], z_1 in Z[1], q_1 in Qv[1], d_0 in D[0], d_{-1} in D[1]
   MBL_TRY(launch_binit<T>(b, Q, precond, src, scale_dev, Z[0], Z[1], Qv[1], D[0], D[1], x,
@@ -943,7 +948,7 @@ static mbl_status bminres_core(mbl_basis_s* b, mbl_batch_s* bw, const BatchDev& 
   auto iteration = [&](int64_t k, hipStream_t st) -> mbl_status {
     const BGivens gv = givens_args(k);
     MBL_TRY((launch_bapply<T, 1, true>(b, Q, gv, Qv[k % kRing], P, bw->partials1, st)));
-    if (k > kDxGroup && (k - 1) % kDxGroup == 0) MBL_TRY(dx_group(k - kDxGroup, kDxGroup, st));
+    if (k > dxg && (k - 1) % dxg == 0) MBL_TRY(dx_group(k - dxg, dxg, st));
     MBL_TRY(launch_bzq<T>(b, Q, precond, gv.Scur, bw->partials1, bw->alph + (k & 1) * R, P,
                           Z[k & 1], Z[(k + 1) & 1], Qv[(k + 1) % kRing], bw->partials2, st));
     return MBL_OK;
@@ -954,7 +959,7 @@ static mbl_status bminres_core(mbl_basis_s* b, mbl_batch_s* bw, const BatchDev& 
     BGivens gv = givens_args(K + 1);
     hipLaunchKernelGGL(k_bgivens_last, dim3(1), dim3(kBWG), 0, st, gv, R);
     MBL_HIP(hipGetLastError());
-    const int64_t covered = K >= 1 ? kDxGroup * ((K - 1) / kDxGroup) : 0;
+    const int64_t covered = K >= 1 ? dxg * ((K - 1) / dxg) : 0;
     if (K > covered) MBL_TRY(dx_group(covered + 1, (int)(K - covered), st));
     return MBL_OK;
   };
@@ -964,7 +969,7 @@ static mbl_status bminres_core(mbl_basis_s* b, mbl_batch_s* bw, const BatchDev& 
   // captured once per workspace and replayed (a replay after convergence is
   // a sequence of no-op launches). tol and kmax are kernel arguments, so the
   // graph is captured again when they change.
-  constexpr int64_t kGraphIters = 16;
+  const int64_t kGraphIters = bw->sched_graph;
   const int ti = std::is_same<T, float>::value ? 1 : 0;
   if (bw->graph_mode < 0) {
     const char* e = getenv("MBL_BATCH_GRAPHS");
@@ -1007,7 +1012,7 @@ static mbl_status bminres_core(mbl_basis_s* b, mbl_batch_s* bw, const BatchDev& 
   // (marked fresh) in the slot the Givens step of iteration K reads
   auto restart_lanes = [&](const std::vector<int>& restart, const double* rhs) -> mbl_status {
     const int64_t K = issued + 1;
-    if (K % kDxGroup != 2 || kGraphIters % kRing != 0) {
+    if (K % dxg != 2 % dxg || kGraphIters % kRing != 0) {
       set_error("internal: streaming restart off the iteration grid");
       return MBL_ERR_NUMERIC;
     }
@@ -1108,7 +1113,7 @@ static mbl_status bminres_run(mbl_basis_s* b, mbl_batch_s* bw, int precision, in
                               std::vector<int64_t>& iters, std::vector<double>& phi) {
   const int R = bw->R;
   const int64_t n = b->n;
-  BatchDev Q{bw->h, bw->c0, R};
+  BatchDev Q{bw->h, bw->c0, R, bw->sched_grid};
   iters.assign(R, 0);
   phi.assign(R, 0.0);
   std::vector<double> sc(R);
@@ -1135,7 +1140,7 @@ static mbl_status bminres_run(mbl_basis_s* b, mbl_batch_s* bw, int precision, in
   std::vector<int> fp32_phase(R, 1);
   for (int cycle = 0;; ++cycle) {
     MBL_TRY(launch_bresidual(b, Q, precond, rhs, x, bw->r64, bw->partials1, s));
-    MBL_TRY(breduce_host(bw, bw->partials1, bgrid(b, R), 2, sums.data(), s));
+    MBL_TRY(breduce_host(bw, bw->partials1, bgrid(b, R, Q.grid), 2, sums.data(), s));
     bool any = false, any_fp64 = false;
     double worst = 0;
     for (int r = 0; r < R; ++r) {
@@ -1169,7 +1174,7 @@ static mbl_status bminres_run(mbl_basis_s* b, mbl_batch_s* bw, int precision, in
         std::vector<double> ones(R, 1.0);
         MBL_TRY(baxpby(bw, n, ones, bw->t64, ones, x, s));
         MBL_TRY(launch_bresidual(b, Q, precond, rhs, x, bw->r64, bw->partials1, s));
-        MBL_TRY(breduce_host(bw, bw->partials1, bgrid(b, R), 2, sums.data(), s));
+        MBL_TRY(breduce_host(bw, bw->partials1, bgrid(b, R, Q.grid), 2, sums.data(), s));
         for (int r = 0; r < R; ++r) phi[r] = std::sqrt(sums[2 * r]);
       }
       break;
@@ -1235,7 +1240,7 @@ double gershgorin_bound(const mbl_basis_s* b, const double* h);
 // norms ||(H_r - shift_r) v_r|| for all r (fields uploaded with shifts)
 static mbl_status bapply_norms(mbl_basis_s* b, mbl_batch_s* bw, const double* v, double* out,
                                hipStream_t s) {
-  BatchDev Q{bw->h, bw->c0, bw->R};
+  BatchDev Q{bw->h, bw->c0, bw->R, bw->sched_grid};
   MBL_TRY((launch_bapply<double, 0, false>(b, Q, BGivens{}, v, bw->t64, nullptr, s)));
   MBL_TRY(bdot_host(bw, b->n, bw->t64, bw->t64, out, s));
   for (int r = 0; r < bw->R; ++r) out[r] = std::sqrt(out[r]);
@@ -1481,7 +1486,7 @@ mbl_status bstream_si_lanczos(mbl_basis b, mbl_batch bw, StreamProblem* P, int n
     return MBL_ERR_ARG;
   }
   const bool verbose = std::getenv("MBL_VERBOSE") != nullptr;
-  const int G = bgrid(b, R);
+  const int G = bgrid(b, R, bw->sched_grid);
   const int GC = std::max<int>(1, std::min<int64_t>(256, (n + 255) / 256));   // CGS groups
   DevMem mask, part, kidx, part3, U, vtmp;
   MBL_TRY(dev_alloc(mask, sizeof(int) * R));
@@ -1864,7 +1869,7 @@ mbl_status bstream_si_lanczos(mbl_basis b, mbl_batch bw, StreamProblem* P, int n
     }
     return MBL_OK;
   };
-  BatchDev Q{bw->h, bw->c0, R};
+  BatchDev Q{bw->h, bw->c0, R, bw->sched_grid};
   std::vector<BState> fin;
   MBL_TRY(bminres_core<double>(b, bw, Q, precond, bw->V, bw->scale, bw->x, minres_tol,
                                minres_kmax, s, fin, &hook));
@@ -2003,6 +2008,31 @@ mbl_status mbl_batch_bytes(mbl_batch w, int64_t* bytes) {
   return MBL_OK;
 }
 
+mbl_status mbl_batch_set_schedule(mbl_batch w, int grid, int graph_iters, int dx_group) {
+  clear_error();
+  MBL_ARG(w, "NULL argument");
+  MBL_ARG(grid == 0 || (grid >= 8 && grid <= kBGrid && grid % 8 == 0),
+          "grid must be 0 or a multiple of 8 in [8, 512]");
+  MBL_ARG(graph_iters == 0 || graph_iters == 8 || graph_iters == 16 || graph_iters == 32,
+          "graph_iters must be 0, 8, 16 or 32");
+  MBL_ARG(dx_group == 0 || dx_group == 1 || dx_group == 2 || dx_group == 4,
+          "dx_group must be 0, 1, 2 or 4");
+  const int g = graph_iters ? graph_iters : 16, d = dx_group ? dx_group : 4;
+  if (grid != w->sched_grid || g != w->sched_graph || d != w->sched_dx) {
+    // captured MINRES graphs hold the old launch shapes
+    for (auto& row : w->graph)
+      for (auto& gx : row)
+        if (gx) {
+          (void)hipGraphExecDestroy(gx);
+          gx = nullptr;
+        }
+  }
+  w->sched_grid = grid;
+  w->sched_graph = g;
+  w->sched_dx = d;
+  return MBL_OK;
+}
+
 mbl_status mbl_apply_H_batched(mbl_basis b, mbl_batch w, const double* h_host,
                                const double* sigma_host, const double* x_dev, double* y_dev,
                                void* stream) {
@@ -2015,7 +2045,7 @@ mbl_status mbl_apply_H_batched(mbl_basis b, mbl_batch w, const double* h_host,
             "non-finite h or sigma");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   MBL_TRY(bupload(w, h_host, sigma_host, s));
-  BatchDev Q{w->h, w->c0, w->R};
+  BatchDev Q{w->h, w->c0, w->R, w->sched_grid};
   return launch_bapply<double, 0, false>(b, Q, BGivens{}, x_dev, y_dev, nullptr, s);
 }
 
@@ -2031,7 +2061,7 @@ mbl_status mbl_apply_H_batched_f32(mbl_basis b, mbl_batch w, const double* h_hos
             "non-finite h or sigma");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   MBL_TRY(bupload(w, h_host, sigma_host, s));
-  BatchDev Q{w->h, w->c0, w->R};
+  BatchDev Q{w->h, w->c0, w->R, w->sched_grid};
   return launch_bapply<float, 0, false>(b, Q, BGivens{}, x_dev, y_dev, nullptr, s);
 }
 
@@ -2097,7 +2127,7 @@ mbl_status mbl_twist_expect_batched(mbl_basis b, mbl_batch w, const double* psi_
   MBL_ARG(nvec >= 1, "nvec must be >= 1");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int R = w->R, L = b->L;
-  const int G = bgrid(b, R);
+  const int G = bgrid(b, R, w->sched_grid);
   MBL_ARG((size_t)G * R * 2 <= w->part_elems, "internal: partials too small");
   BTwistTab T{};
   const double pi = 3.14159265358979323846;
@@ -2105,7 +2135,7 @@ mbl_status mbl_twist_expect_batched(mbl_basis b, mbl_batch w, const double* psi_
     T.c[m] = std::cos(pi * m / L);
     T.s[m] = std::sin(pi * m / L);
   }
-  BatchDev Q{w->h, w->c0, R};
+  BatchDev Q{w->h, w->c0, R, w->sched_grid};
   const size_t lds = blds_bytes(R, L, b->nlo);
   const int64_t NR = b->n * R;
   for (int t = 0; t < nvec; ++t) {

@@ -30,6 +30,7 @@ struct BatchDev {
   const double* h;     // R x L fields
   const double* c0;    // R: L/4 + (1/2) sum h - sigma
   int R;
+  int grid;            // workgroups of the row kernels; 0: one per compute unit (host only)
 };
 
 // LDS layout (bytes): lo_rank (2^nlo uint16) at offset 0, so a rank read is

@@ -120,6 +120,7 @@ def disorder_scan(Ls, hs, R=32, nev=20, first_seed=0):
         b = mbl.Basis(L, tune.best_lo_bits(L, R, "fp64"))
         mmax = min(b.n, 3 * nev + 40)
         bt = mbl.Batch(b, R, mmax=mmax, nevmax=nev)
+        tune.apply_schedule(bt, L, R, "fp64")
         for h in hs:
             fields = [disorder_fields(L, h, first_seed + r) for r in range(R)]
             t0 = time.perf_counter()
