@@ -14,6 +14,14 @@
   eigenstates; the row reports their mean and standard deviation over
   realizations, next to the GOE and Poisson ratios and the random-state entropy of Sec. IV B, and
   the per-realization values (with sigma and the eigenvalues).
+* ``grad``: eigenpair derivatives for many realizations (the L = 20, h = 3,
+  16 realizations, 4 pairs form): the nev pairs nearest each realization's
+  spectral midpoint from one problem-array call, then dE/dh_j and
+  d|z|^2/dh_j for every site and every converged pair (Hellmann-Feynman and
+  one adjoint MINRES solve, Sec. III), with the two sum rules that hold
+  exactly in the S^z = 0 sector (a uniform field shift changes neither the
+  eigenvectors nor, summed over sites, the energy): sum_j dE/dh_j = 0 and
+  sum_j d|z|^2/dh_j = 0; seconds per pair for both parts.
 * ``eig``: one full shift-invert Lanczos run (sigma at the spectral midpoint,
   the nev pairs nearest it, MINRES tol 1e-12, eig_tol 1e-10), its time per
   converged eigenpair, steps and MINRES iterations (set MBL_VERBOSE=1 for a
@@ -22,6 +30,7 @@
     python -m paper_2203_09732_amd.studies precond --L 12 14 16 18 20 --h 3 4 --seeds 0 1
     python -m paper_2203_09732_amd.studies memory --L 12 14 16 18 20 22 24 26
     MBL_VERBOSE=1 python -m paper_2203_09732_amd.studies eig --L 22 --h 3.5 --nev 4
+    python -m paper_2203_09732_amd.studies grad --L 20 --h 3 --R 16 --nev 4
 
 One JSON object per line on stdout.
 """
@@ -32,6 +41,8 @@ import json
 import os
 import sys
 import time
+
+import numpy as np
 
 
 def precond_iterations(Ls, hs, seeds, kinds=("id", "jacobi", "row"), tol=1e-12, kmax_per_n=30):
@@ -107,6 +118,48 @@ def eigen_run(L, h, seed, nev, precision="fp64"):
            "evals": [float(e) for e in res.evals], "abs_z": [float(abs(v)) for v in z]}
 
 
+def grad_study(L, h, R=16, nev=4, first_seed=0, tol=1e-12):
+    import torch
+
+    import paper_2203_09732_amd as mbl
+    from workloads import disorder_fields
+    fields = [disorder_fields(L, h, first_seed + r) for r in range(R)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st, res = mbl.si_lanczos_problems([dict(L=L, h=f, nev=nev) for f in fields], seed=first_seed)
+    torch.cuda.synchronize()
+    t_eig = time.perf_counter() - t0
+    b = mbl.Basis(L)
+    ws = mbl.Workspace(b, 0)
+    rows, npairs, t_adj = [], 0, 0.0
+    for r, (f, p) in enumerate(zip(fields, res)):
+        pairs = []
+        for t in range(len(p.evals) if p.status == 0 else 0):   # converged realizations
+            psi = p.evecs[:, t].contiguous()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            dE, dz2, z, info = mbl.eig_grad(b, f, float(p.evals[t]), psi, tol=tol, ws=ws)
+            torch.cuda.synchronize()
+            t_adj += time.perf_counter() - t1
+            npairs += 1
+            pairs.append({"E": float(p.evals[t]), "abs_z": abs(z), "adjoint_iters": int(info.iters),
+                          "adjoint_status": int(info.status),
+                          "sum_dE": float(dE.sum()), "sum_dz2": float(dz2.sum()),
+                          "max_abs_dz2": float(np.abs(dz2).max()),
+                          "dE": [float(v) for v in dE], "dz2": [float(v) for v in dz2]})
+        rows.append({"study": "grad", "L": L, "h": h, "seed": first_seed + r, "sigma": p.sigma,
+                     "status": p.status, "nconv": p.nconv, "steps": p.steps, "pairs": pairs})
+        yield rows[-1]
+    yield {"study": "grad_summary", "L": L, "n": b.n, "h": h, "R": R, "nev": nev,
+           "converged_pairs": npairs, "eig_seconds": round(t_eig, 2),
+           "eig_s_per_pair": round(t_eig / max(npairs, 1), 3),
+           "adjoint_seconds": round(t_adj, 2), "adjoint_s_per_pair": round(t_adj / max(npairs, 1), 3),
+           "max_abs_sum_dE": max((abs(q["sum_dE"]) for r_ in rows for q in r_["pairs"]),
+                                 default=float("nan")),
+           "max_rel_sum_dz2": max((abs(q["sum_dz2"]) / max(1.0, q["max_abs_dz2"])
+                                   for r_ in rows for q in r_["pairs"]), default=float("nan"))}
+
+
 def disorder_scan(Ls, hs, R=32, nev=20, first_seed=0):
     import math
 
@@ -165,7 +218,7 @@ def disorder_scan(Ls, hs, R=32, nev=20, first_seed=0):
 def main(argv=None):
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["precond", "memory", "eig", "scan"])
+    ap.add_argument("study", choices=["precond", "memory", "eig", "scan", "grad"])
     ap.add_argument("--L", type=int, nargs="+", default=[12, 14, 16, 18])
     ap.add_argument("--h", type=float, nargs="+", default=[3.0, 4.0])
     ap.add_argument("--seeds", type=int, nargs="+", default=[0, 1])
@@ -180,6 +233,8 @@ def main(argv=None):
         rows = memory_curve(a.L, a.mmax)
     elif a.study == "scan":
         rows = disorder_scan(a.L, a.h, a.R, a.nev, a.seeds[0])
+    elif a.study == "grad":
+        rows = (r for L in a.L for r in grad_study(L, a.h[0], a.R, a.nev, a.seeds[0]))
     else:
         rows = (r for L in a.L for r in eigen_run(L, a.h[0], a.seeds[0], a.nev, a.precision))
     for r in rows:

@@ -68,3 +68,28 @@ def test_memory_curve_measured_against_linear_model(gpu):
         assert taken >= model_b
         # per-allocation rounding (about 20 buffers) and the small fixed part
         assert taken <= 1.1 * model_b + 64 * 2**20
+
+
+def test_grad_study_matches_oracle(gpu):
+    """The gradient study's path (problem-array eigenpairs, then eig_grad per
+    pair) at L = 10, 3 realizations, 2 pairs: dE/dh against the oracle's
+    Hellmann-Feynman -<S^z_j> of its own dense eigenvector and d|z|^2/dh
+    against the oracle's perturbation sum, at the bars of the adjoint tests;
+    the sum rules the study reports."""
+    from oracle import adjoint, model
+    from paper_2203_09732_amd import studies
+    from workloads import disorder_fields
+    L, h, R, nev = 10, 3.0, 3, 2
+    rows = list(studies.grad_study(L, h, R=R, nev=nev, first_seed=50))
+    summary = rows[-1]
+    assert summary["study"] == "grad_summary" and summary["converged_pairs"] == R * nev
+    assert summary["max_abs_sum_dE"] <= 1e-11 and summary["max_rel_sum_dz2"] <= 1e-8
+    for row in rows[:-1]:
+        f = disorder_fields(L, h, row["seed"])
+        w = np.linalg.eigvalsh(model.hamiltonian_dense(L, f))
+        for q in row["pairs"]:
+            k = int(np.argmin(np.abs(w - q["E"])))
+            _, psi_ref, dpsi = adjoint.eigvec_derivatives(L, f, k)
+            assert np.abs(np.array(q["dE"]) - adjoint.hellmann_feynman(L, psi_ref)).max() <= 5e-10
+            dz2_ref = adjoint.dz2_dh(L, psi_ref, dpsi)
+            assert np.abs(np.array(q["dz2"]) - dz2_ref).max() <= 1e-7 * max(1.0, np.abs(dz2_ref).max())
