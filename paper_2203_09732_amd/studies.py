@@ -22,6 +22,12 @@
   exactly in the S^z = 0 sector (a uniform field shift changes neither the
   eigenvectors nor, summed over sites, the energy): sum_j dE/dh_j = 0 and
   sum_j d|z|^2/dh_j = 0; seconds per pair for both parts.
+* ``mixed``: the mixed-precision form against FP64 on the same realization
+  (config 3's deliverable at a size one run can hold): SI-Lanczos with FP64
+  MINRES and with FP32-inner MINRES from the same start vector; the
+  eigenvalue differences |E_32 - E_64| / max(|E_64|, 1), the eigenvector
+  overlap deficits 1 - |<u_32, u_64>|, the twist differences, the explicit
+  residuals of both, and seconds per pair of both.
 * ``eig``: one full shift-invert Lanczos run (sigma at the spectral midpoint,
   the nev pairs nearest it, MINRES tol 1e-12, eig_tol 1e-10), its time per
   converged eigenpair, steps and MINRES iterations (set MBL_VERBOSE=1 for a
@@ -31,6 +37,7 @@
     python -m paper_2203_09732_amd.studies memory --L 12 14 16 18 20 22 24 26
     MBL_VERBOSE=1 python -m paper_2203_09732_amd.studies eig --L 22 --h 3.5 --nev 4
     python -m paper_2203_09732_amd.studies grad --L 20 --h 3 --R 16 --nev 4
+    python -m paper_2203_09732_amd.studies mixed --L 20 --h 3.5 --nev 4
 
 One JSON object per line on stdout.
 """
@@ -116,6 +123,41 @@ def eigen_run(L, h, seed, nev, precision="fp64"):
            "s_per_pair": round(dt / max(res.nconv, 1), 2),
            "max_resid_over_escale": float(max(res.resid) / escale),
            "evals": [float(e) for e in res.evals], "abs_z": [float(abs(v)) for v in z]}
+
+
+def mixed_study(L, h, seed, nev):
+    import torch
+
+    import paper_2203_09732_amd as mbl
+    from workloads import disorder_fields
+    b = mbl.Basis(L)
+    f = disorder_fields(L, h, seed)
+    lo, hi, sigma = mbl.sigma_midpoint(b, f, 1e-12)
+    escale = max(abs(lo), abs(hi))
+    out = {"study": "mixed", "L": L, "n": b.n, "h": h, "seed": seed, "nev": nev, "sigma": sigma,
+           "escale": escale}
+    res = {}
+    for prec in ("fp64", "fp32_inner"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = mbl.si_lanczos(b, f, sigma, nev, escale=escale, seed=seed, precision=prec)
+        z = mbl.twist_expect(b, r.evecs)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        res[prec] = (r, z)
+        out[prec] = {"seconds": round(dt, 2), "s_per_pair": round(dt / max(r.nconv, 1), 3),
+                     "nconv": int(r.nconv), "steps": int(r.steps),
+                     "minres_iters": int(r.minres_iters),
+                     "max_rel_resid": float(max(r.resid) / escale)}
+    (r64, z64), (r32, z32) = res["fp64"], res["fp32_inner"]
+    if r64.nconv == nev and r32.nconv == nev:
+        ov = torch.abs(torch.sum(r64.evecs * r32.evecs, dim=0)).cpu().numpy()
+        out["max_rel_dE"] = float(np.max(np.abs(r32.evals - r64.evals) /
+                                         np.maximum(np.abs(r64.evals), 1.0)))
+        out["max_overlap_deficit"] = float(np.max(1.0 - ov))
+        out["max_dz"] = float(np.max(np.abs(z32 - z64)))
+    out["time_ratio_fp32_over_fp64"] = round(out["fp32_inner"]["seconds"] / out["fp64"]["seconds"], 3)
+    yield out
 
 
 def grad_study(L, h, R=16, nev=4, first_seed=0, tol=1e-12):
@@ -218,7 +260,7 @@ def disorder_scan(Ls, hs, R=32, nev=20, first_seed=0):
 def main(argv=None):
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     ap = argparse.ArgumentParser()
-    ap.add_argument("study", choices=["precond", "memory", "eig", "scan", "grad"])
+    ap.add_argument("study", choices=["precond", "memory", "eig", "scan", "grad", "mixed"])
     ap.add_argument("--L", type=int, nargs="+", default=[12, 14, 16, 18])
     ap.add_argument("--h", type=float, nargs="+", default=[3.0, 4.0])
     ap.add_argument("--seeds", type=int, nargs="+", default=[0, 1])
@@ -233,6 +275,8 @@ def main(argv=None):
         rows = memory_curve(a.L, a.mmax)
     elif a.study == "scan":
         rows = disorder_scan(a.L, a.h, a.R, a.nev, a.seeds[0])
+    elif a.study == "mixed":
+        rows = (r for L in a.L for s_ in a.seeds for r in mixed_study(L, a.h[0], s_, a.nev))
     elif a.study == "grad":
         rows = (r for L in a.L for r in grad_study(L, a.h[0], a.R, a.nev, a.seeds[0]))
     else:
