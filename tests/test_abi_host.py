@@ -61,6 +61,65 @@ def test_null_handles_rejected(mbl):
     assert mbl.lib.mbl_dot(0, None, None, C.byref(out), None) == mbl.OK and out.value == 0.0
 
 
+def _problem(mbl, L, nev, h=None, sigma=float("nan")):
+    """One mbl_problem with host arrays kept alive on the returned object and
+    a non-NULL fake device pointer (never touched: these calls fail argument
+    checks before any device work)."""
+    p = mbl.Problem()
+    hh = np.zeros(L) if h is None else np.asarray(h, dtype=np.float64)
+    ev = np.zeros(max(nev, 1))
+    p._keep = (hh, ev)
+    p.L, p.nev = L, nev
+    p.h_host = hh.ctypes.data_as(C.POINTER(C.c_double))
+    p.sigma, p.escale = sigma, 0.0
+    p.evecs_dev = 0x1000
+    p.evals_host = ev.ctypes.data_as(C.POINTER(C.c_double))
+    return p
+
+
+@pytest.mark.parametrize("case", ["odd L", "L too large", "nev 0", "nev > 32", "nan field",
+                                  "inf sigma", "nev > n"])
+def test_problem_array_rejects_bad_problems_on_the_host(mbl, case):
+    L, nev, h, sigma = 10, 2, None, float("nan")
+    if case == "odd L":
+        L = 11
+    elif case == "L too large":
+        L = 34
+    elif case == "nev 0":
+        nev = 0
+    elif case == "nev > 32":
+        nev = 33
+    elif case == "nan field":
+        h = np.full(10, np.nan)
+    elif case == "inf sigma":
+        sigma = float("inf")
+    elif case == "nev > n":
+        L, nev = 4, 7          # C(4, 2) = 6 states
+    arr = (mbl.Problem * 1)(_problem(mbl, L, nev, h, sigma))
+    st = mbl.lib.mbl_si_lanczos_problems(arr, 1, 0, 1e-12, 1000, 1e-10, 1e-5, 0, 0, None)
+    assert st == mbl.ERR_ARG, (case, mbl.lib.mbl_last_error().decode())
+
+
+def test_problem_array_rejects_bad_call_arguments_on_the_host(mbl, monkeypatch):
+    arr = (mbl.Problem * 1)(_problem(mbl, 10, 2))
+    call = mbl.lib.mbl_si_lanczos_problems
+    assert call(None, 1, 0, 1e-12, 1000, 1e-10, 1e-5, 0, 0, None) == mbl.ERR_ARG
+    assert call(arr, 0, 0, 1e-12, 1000, 1e-10, 1e-5, 0, 0, None) == mbl.ERR_ARG
+    assert call(arr, 1, 129, 1e-12, 1000, 1e-10, 1e-5, 0, 0, None) == mbl.ERR_ARG   # mmax
+    assert call(arr, 1, 0, 0.0, 1000, 1e-10, 1e-5, 0, 0, None) == mbl.ERR_ARG       # minres_tol
+    assert call(arr, 1, 0, 1e-12, 0, 1e-10, 1e-5, 0, 0, None) == mbl.ERR_ARG        # kmax
+    assert call(arr, 1, 0, 1e-12, 1000, -1.0, 1e-5, 0, 0, None) == mbl.ERR_ARG      # eig_tol
+    assert call(arr, 1, 0, 1e-12, 1000, 1e-10, 1e-5, 0, 3, None) == mbl.ERR_ARG     # precond
+    for bad in ("7", "18", "2"):
+        monkeypatch.setenv("MBL_PERSISTENT_MAX_L", bad)
+        assert call(arr, 1, 0, 1e-12, 1000, 1e-10, 1e-5, 0, 0, None) == mbl.ERR_ARG
+        assert "MBL_PERSISTENT_MAX_L" in mbl.lib.mbl_last_error().decode()
+
+
+def test_batch_schedule_rejects_null_handle(mbl):
+    assert mbl.lib.mbl_batch_set_schedule(None, 0, 0, 0) == mbl.ERR_ARG
+
+
 @pytest.mark.parametrize("k,seed", [(1, 0), (2, 1), (7, 2), (60, 3), (250, 4)])
 def test_tridiag_eig_matches_lapack(mbl, k, seed):
     rng = np.random.default_rng(seed)
