@@ -342,7 +342,7 @@ mbl_status mbl_twist_expect_batched(mbl_basis b, mbl_batch w, const double* psi_
  * workspace share every MINRES launch, but each lane takes its own Lanczos
  * steps (its solve restarted in flight on v_{k+1} when it ends) and, when
  * its realization has converged, the next one (sigma found per realization
- * first). The environment variable MBL_PERSISTENT_MAX_L (even, 4..16)
+ * first). The environment variable MBL_PERSISTENT_MAX_L (even, 10..16)
  * lowers the longest chain of the persistent launch.
  * Per problem (inputs): L (even, 4..32), nev (1..min(32, C(L, L/2))),
  * h_host (L fields), sigma (NaN: (E_min + E_max)/2 computed here, Sec. IV A),

@@ -13,6 +13,7 @@
 #include "brows.h"
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <functional>
 #include <cmath>
@@ -728,18 +729,22 @@ namespace mbl {
 // resident workgroup per CU slows the gather-bound apply), whole XCD slices
 // once large.
 static int device_cus(int device) {
-  static int cached[64] = {0};
+  // per-device cache; calls from several host threads may fill it at once
+  // (they store the same value)
+  static std::atomic<int> cached[64];
   if (device < 0 || device >= 64) return 256;
-  if (cached[device] == 0) {
+  int c = cached[device].load(std::memory_order_relaxed);
+  if (c == 0) {
     int v = 0;
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
         v <= 0) {
       (void)hipGetLastError();
       v = 256;
     }
-    cached[device] = v;
+    cached[device].store(v, std::memory_order_relaxed);
+    c = v;
   }
-  return cached[device];
+  return c;
 }
 
 static int bgrid(const mbl_basis_s* b, int R, int grid = 0) {

@@ -1151,11 +1151,12 @@ extern "C" mbl_status mbl_si_lanczos_problems(mbl_problem* probs, int nprob, int
   MBL_ARG(precond >= 0 && precond <= 2, "unknown preconditioner");
   MBL_ARG(mmax == 0 || (mmax >= 1 && mmax <= kWgMaxM), "mmax must be 0 or in [1, 128]");
   // the longest chain of the persistent launch: 16, or MBL_PERSISTENT_MAX_L
-  // (even, 4..16) to send shorter chains to the streaming batches as well
+  // (even, 10..16) to send shorter chains to the streaming batches as well
+  // (the batched kernels have instances from L = 12 on)
   int max_small = kWgMaxL;
   if (const char* e = std::getenv("MBL_PERSISTENT_MAX_L")) {
     const int v = std::atoi(e);
-    MBL_ARG(v >= 4 && v <= kWgMaxL && v % 2 == 0, "MBL_PERSISTENT_MAX_L must be even in [4, 16]");
+    MBL_ARG(v >= 10 && v <= kWgMaxL && v % 2 == 0, "MBL_PERSISTENT_MAX_L must be even in [10, 16]");
     max_small = v;
   }
   std::vector<int> small, large, mm(nprob);

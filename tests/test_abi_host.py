@@ -110,7 +110,7 @@ def test_problem_array_rejects_bad_call_arguments_on_the_host(mbl, monkeypatch):
     assert call(arr, 1, 0, 1e-12, 0, 1e-10, 1e-5, 0, 0, None) == mbl.ERR_ARG        # kmax
     assert call(arr, 1, 0, 1e-12, 1000, -1.0, 1e-5, 0, 0, None) == mbl.ERR_ARG      # eig_tol
     assert call(arr, 1, 0, 1e-12, 1000, 1e-10, 1e-5, 0, 3, None) == mbl.ERR_ARG     # precond
-    for bad in ("7", "18", "2"):
+    for bad in ("7", "18", "8", "11"):
         monkeypatch.setenv("MBL_PERSISTENT_MAX_L", bad)
         assert call(arr, 1, 0, 1e-12, 1000, 1e-10, 1e-5, 0, 0, None) == mbl.ERR_ARG
         assert "MBL_PERSISTENT_MAX_L" in mbl.lib.mbl_last_error().decode()
