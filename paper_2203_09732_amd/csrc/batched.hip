@@ -293,6 +293,173 @@ __global__ void k_binit_state(const double* __restrict__ partials, int G, int R,
   }
 }
 
+// ---- block-staged plain product (split nlo = 10, R = 32) ---------------------
+// y_r = (H_r - sigma_r) x_r with the per-row arithmetic of k_bapply<double,
+// 0, false> (the same terms in the same order), for bases split at nlo = 10
+// (a hi block holds at most C(10, 5) = 252 rows, 252 x 256 B of x at R = 32).
+// Each workgroup owns a host-built list of whole blocks: the blocks of one
+// eighth of the rows go to that eighth's XCD, balanced by rows between its
+// workgroups. While it computes block i, the workgroup stages block i + 1 of x
+// in LDS by LDS DMA (buffer_load ... lds); the low-bond neighbours then come
+// from LDS, the split-bond, wrap-bond and high-bond neighbours from memory,
+// the far ones (high bonds b >= kStageFar and the wrap bond) by non-temporal
+// loads, since they are not reused before their lines leave L2.
+constexpr int kStageNlo = 10, kStageR = 32, kStageCap = 252, kStageFar = 7;
+
+struct StagedBlock {
+  uint32_t hi, row0, cnt, coff;   // block, its first row and row count, lo_state offset
+  uint32_t sb_bnd, sb_wrap;       // byte offsets of the blocks hi ^ 1 and hi ^ 2^(nhi - 1)
+  uint32_t pad0, pad1;
+  uint32_t sbh[24];               // byte offsets of the blocks hi ^ (3 << b), b < nhi - 1
+};
+
+__device__ __forceinline__ double2 bld_nt(__amdgpu_buffer_rsrc_t r, uint32_t v, uint32_t so) {
+  const auto u = __builtin_amdgcn_raw_buffer_load_b128(r, (int)v, (int)so, 2);   // nt
+  double2 d;
+  __builtin_memcpy(&d, &u, sizeof(d));
+  return d;
+}
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+template <int L>
+__global__ __launch_bounds__(kBWG) void k_bapply_staged(DevBasis B, BatchDev Q,
+                                                        const StagedBlock* __restrict__ blocks,
+                                                        const int* __restrict__ wg_first,
+                                                        const double* __restrict__ x,
+                                                        double* __restrict__ y) {
+  constexpr int NLO = kStageNlo, R = kStageR, NHI = L - NLO;
+  constexpr int PR = R / 2, RPW = 64 / PR, ROWB = R * 8, NW = kBWG / 64;
+  constexpr int NNIB = (NLO + 3) / 4;
+  __shared__ __align__(16) double bufA[kStageCap * R];
+  __shared__ __align__(16) double bufB[kStageCap * R];
+  __shared__ __align__(16) uint16_t s_rank[1 << NLO];
+  __shared__ __align__(16) uint16_t s_state[1 << NLO];
+  __shared__ __align__(16) double s_lut[NNIB * 16 * R];   // low-bit field sums
+  __shared__ __align__(16) double s_c0[R];
+  __shared__ __align__(16) double s_fA[R];                // high-bit field sum of a block
+  __shared__ __align__(16) double s_fB[R];
+  __shared__ __align__(16) double s_h[R * L];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const uint32_t wave = uni(tid >> 6);
+  const int first = wg_first[blockIdx.x], last = wg_first[blockIdx.x + 1];
+  for (int t = tid; t < (1 << NLO); t += kBWG) {
+    s_rank[t] = B.lo_rank[t];
+    s_state[t] = B.lo_state[t];
+  }
+  for (int t = tid; t < NNIB * 16 * R; t += kBWG) {
+    const int r = t % R, kv = t / R, k = kv >> 4, v = kv & 15;
+    double acc = 0.0;
+    for (int bb = 0; bb < 4; ++bb) {
+      const int site = 4 * k + bb;
+      if (site < NLO && ((v >> bb) & 1)) acc += Q.h[r * L + site];
+    }
+    s_lut[t] = acc;
+  }
+  if (tid < R) s_c0[tid] = Q.c0[tid];
+  for (int t = tid; t < R * L; t += kBWG) s_h[t] = Q.h[t];
+  const uint32_t nbytes = (uint32_t)B.n * ROWB;
+  const __amdgpu_buffer_rsrc_t rx = brsrc(x, nbytes), ry = brsrc(y, nbytes);
+  // issue the LDS DMA of block blk into buf (1 KB per wave instruction) and
+  // the block's high-bit field sums
+  auto stage = [&](const StagedBlock& blk, double* buf, double* fh) {
+    const uint32_t hi = uni(blk.hi), row0 = uni(blk.row0), cnt = uni(blk.cnt);
+    const uint32_t nb = cnt * ROWB, ninst = (nb + 1023) >> 10;
+    for (uint32_t i = wave; i < ninst; i += NW) {
+      const uint32_t off = i * 1024 + lane * 16;
+      if (off < nb)
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rx, (lds_void_t*)((char*)buf + i * 1024), 16,
+                                                 row0 * ROWB + off, 0, 0, 0);
+    }
+    if (tid < R) {
+      double f = 0.0;
+      for (int bb = 0; bb < NHI; ++bb)
+        if ((hi >> bb) & 1u) f += s_h[tid * L + NLO + bb];
+      fh[tid] = f;
+    }
+  };
+  auto compute = [&](const StagedBlock& o, const double* buf, const double* fh) {
+    const uint32_t hi = uni(o.hi), cnt = uni(o.cnt), coff = uni(o.coff);
+    const uint32_t sb_bnd = uni(o.sb_bnd), sb_wrap = uni(o.sb_wrap);
+    uint32_t sbh[NHI - 1];
+#pragma unroll
+    for (int bb = 0; bb + 1 < NHI; ++bb) sbh[bb] = uni(o.sbh[bb]);
+    const uint32_t hflips = uni(hi ^ (hi >> 1));
+    const int p = lane % PR;
+    const uint32_t slot = lane / PR;
+    const double f0 = fh[2 * p], f1 = fh[2 * p + 1];
+    const double cc0 = s_c0[2 * p], cc1 = s_c0[2 * p + 1];
+    const uint32_t loff = (uint32_t)p * 16;
+    for (uint32_t j0 = wave * RPW; j0 < cnt; j0 += NW * RPW) {
+      const uint32_t j = j0 + slot;
+      if (j >= cnt) continue;
+      const uint32_t lo = s_state[coff + j];
+      const uint32_t a = (hi << NLO) | lo;
+      const uint32_t rbnd = s_rank[lo ^ (1u << (NLO - 1))], rwrap = s_rank[lo ^ 1u];
+      // the gathers from memory first (their latency overlaps the LDS work)
+      double2 vb = {0.0, 0.0}, vw = {0.0, 0.0};
+      if (((lo >> (NLO - 1)) ^ hi) & 1u) vb = BIO<double>::ld(rx, rbnd * ROWB + loff, sb_bnd);
+      double2 vh[NHI - 1];
+#pragma unroll
+      for (int bb = 0; bb + 1 < NHI; ++bb) {
+        vh[bb] = double2{0.0, 0.0};
+        if ((hflips >> bb) & 1u)
+          vh[bb] = bb >= kStageFar ? bld_nt(rx, j * ROWB + loff, sbh[bb])
+                                   : BIO<double>::ld(rx, j * ROWB + loff, sbh[bb]);
+      }
+      if (((hi >> (NHI - 1)) ^ lo) & 1u) vw = bld_nt(rx, rwrap * ROWB + loff, sb_wrap);
+      const double2 own = *reinterpret_cast<const double2*>(buf + j * R + 2 * p);
+      double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+      for (int bb = 0; bb + 1 < NLO; ++bb) {
+        const uint32_t rk = s_rank[lo ^ (3u << bb)];
+        const double2 v = *reinterpret_cast<const double2*>(buf + rk * R + 2 * p);
+        const bool f = ((lo >> bb) ^ (lo >> (bb + 1))) & 1u;
+        a0 += f ? v.x : 0.0;
+        a1 += f ? v.y : 0.0;
+      }
+      a0 += vb.x;
+      a1 += vb.y;
+#pragma unroll
+      for (int bb = 0; bb + 1 < NHI; ++bb) {
+        a0 += vh[bb].x;
+        a1 += vh[bb].y;
+      }
+      a0 += vw.x;
+      a1 += vw.y;
+      constexpr uint32_t mask = (1u << L) - 1u;
+      const int na = __popc(a ^ (((a << 1) | (a >> (L - 1))) & mask));
+      double F0 = f0, F1 = f1;
+#pragma unroll
+      for (int k = 0; k < NNIB; ++k) {
+        const double2 fv = *reinterpret_cast<const double2*>(
+            s_lut + (((k << 4) + ((lo >> (4 * k)) & 15u)) * R) + 2 * p);
+        F0 += fv.x;
+        F1 += fv.y;
+      }
+      const double d0 = cc0 - 0.5 * (double)na - F0, d1 = cc1 - 0.5 * (double)na - F1;
+      double2 yv;
+      yv.x = d0 * own.x + 0.5 * a0;
+      yv.y = d1 * own.y + 0.5 * a1;
+      BIO<double>::st<kStoreStream>(yv, ry, (uni(o.row0) + j) * ROWB + loff, 0);
+    }
+  };
+  __syncthreads();
+  if (first >= last) return;
+  stage(blocks[first], bufA, s_fA);
+  for (int i = first; i < last; i += 2) {
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's DMA into the buffer landed
+    __syncthreads();                      // every wave's did; the other buffer is free
+    if (i + 1 < last) stage(blocks[i + 1], bufB, s_fB);
+    compute(blocks[i], bufA, s_fA);
+    if (i + 1 >= last) break;
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __syncthreads();
+    if (i + 2 < last) stage(blocks[i + 2], bufA, s_fA);
+    compute(blocks[i + 1], bufB, s_fB);
+  }
+}
+
 // ---- the streaming form: one realization's solve restarted in flight ----
 
 // MINRES restart of the realizations with mask[r] != 0 from x0 = 0: z_K =
@@ -718,6 +885,10 @@ struct mbl_batch_s {
   // launch schedule (mbl_batch_set_schedule): row-kernel workgroups (0: one
   // per CU), MINRES iterations per captured graph, iterations per d/x pass
   int sched_grid = 0, sched_graph = 16, sched_dx = 4;
+  // block lists of the staged plain product (nlo = 10, R = 32), built on first use
+  void* stage_blocks = nullptr;
+  int* stage_first = nullptr;
+  int stage_G = 0;
   hipStream_t cap = nullptr;        // capture stream (the caller's may be the null stream)
 };
 
@@ -1892,6 +2063,8 @@ static void free_batch(mbl_batch_s* w) {
                     w->partials2, w->red, w->scale, w->scale2, w->alph};
   for (double* p : bufs) (void)hipFree(p);
   for (double* p : w->q) (void)hipFree(p);
+  if (w->stage_blocks) (void)hipFree(w->stage_blocks);
+  if (w->stage_first) (void)hipFree(w->stage_first);
   (void)hipFree(w->S);
   for (auto& row : w->graph)
     for (auto& gx : row)
@@ -1989,6 +2162,123 @@ static bool pow2(int R) { return R >= 2 && R <= kBMaxR && (R & (R - 1)) == 0; }
 
 using namespace mbl;
 
+namespace mbl {
+
+static bool staged_instance(const mbl_basis_s* b, int R) {
+  return R == kStageR && b->nlo == kStageNlo && (b->L == 14 || b->L == 16 || b->L == 22);
+}
+
+// The staged product's block lists for the workspace's grid: the blocks of
+// one eighth of the rows go to the workgroups of one XCD (workgroup g runs on
+// XCD g % 8), each block to that XCD's workgroup with the fewest rows so far.
+static mbl_status staged_plan(mbl_basis_s* b, mbl_batch_s* w, hipStream_t s) {
+  const int G = w->sched_grid > 0 ? w->sched_grid : std::max(8, device_cus(b->device) / 8 * 8);
+  if (w->stage_blocks && w->stage_G == G) return MBL_OK;
+  if (w->stage_blocks) (void)hipFree(w->stage_blocks);
+  if (w->stage_first) (void)hipFree(w->stage_first);
+  w->stage_blocks = nullptr;
+  w->stage_first = nullptr;
+  const int nhi = b->nhi, nlo = b->nlo;
+  std::vector<uint32_t> hi_off((size_t)1 << nhi), coff(nlo + 2);
+  MBL_HIP(hipMemcpyAsync(hi_off.data(), b->d_hi_off, sizeof(uint32_t) * hi_off.size(),
+                         hipMemcpyDeviceToHost, s));
+  MBL_HIP(hipMemcpyAsync(coff.data(), b->d_lo_coff, sizeof(uint32_t) * coff.size(),
+                         hipMemcpyDeviceToHost, s));
+  MBL_HIP(hipStreamSynchronize(s));
+  struct Blk {
+    uint32_t hi, row0, cnt, coff;
+  };
+  std::vector<Blk> all;
+  for (size_t hi = 0; hi < hi_off.size(); ++hi) {
+    if (hi_off[hi] == 0xffffffffu) continue;
+    const int c = b->half - __builtin_popcountll(hi);
+    if (c < 0 || c > nlo) continue;
+    const uint32_t cnt = coff[c + 1] - coff[c];
+    if (cnt == 0) continue;
+    if (cnt > (uint32_t)kStageCap) {
+      set_error("internal: staged block larger than its LDS buffer");
+      return MBL_ERR_NUMERIC;
+    }
+    all.push_back(Blk{(uint32_t)hi, hi_off[hi], cnt, coff[c]});
+  }
+  const int X = kXcds, per = G / X;
+  std::vector<std::vector<Blk>> wl(G);
+  const uint64_t n = (uint64_t)b->n;
+  size_t bi = 0;
+  for (int xcd = 0; xcd < X; ++xcd) {
+    const uint64_t lim = n * (uint64_t)(xcd + 1) / X;
+    std::vector<uint64_t> load(per, 0);
+    while (bi < all.size() && (all[bi].row0 < lim || xcd == X - 1)) {
+      int best = 0;
+      for (int q = 1; q < per; ++q)
+        if (load[q] < load[best]) best = q;
+      load[best] += all[bi].cnt;
+      wl[xcd + X * best].push_back(all[bi]);
+      ++bi;
+    }
+  }
+  std::vector<StagedBlock> list;
+  std::vector<int> first(1, 0);
+  const uint32_t ROWB = kStageR * 8;
+  for (int g = 0; g < G; ++g) {
+    for (const Blk& v : wl[g]) {
+      StagedBlock d{};
+      d.hi = v.hi;
+      d.row0 = v.row0;
+      d.cnt = v.cnt;
+      d.coff = v.coff;
+      // neighbour blocks that do not exist are only addressed by masked gathers
+      d.sb_bnd = hi_off[v.hi ^ 1u] * ROWB;
+      d.sb_wrap = hi_off[v.hi ^ (1u << (nhi - 1))] * ROWB;
+      for (int bb = 0; bb + 1 < nhi; ++bb) d.sbh[bb] = hi_off[v.hi ^ (3u << bb)] * ROWB;
+      list.push_back(d);
+    }
+    first.push_back((int)list.size());
+  }
+  if (hipMalloc(&w->stage_blocks, sizeof(StagedBlock) * std::max<size_t>(list.size(), 1)) !=
+          hipSuccess ||
+      hipMalloc((void**)&w->stage_first, sizeof(int) * first.size()) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("device allocation failed (staged block lists)");
+    return MBL_ERR_NOMEM;
+  }
+  MBL_HIP(hipMemcpyAsync(w->stage_blocks, list.data(), sizeof(StagedBlock) * list.size(),
+                         hipMemcpyHostToDevice, s));
+  MBL_HIP(hipMemcpyAsync(w->stage_first, first.data(), sizeof(int) * first.size(),
+                         hipMemcpyHostToDevice, s));
+  MBL_HIP(hipStreamSynchronize(s));
+  w->stage_G = G;
+  return MBL_OK;
+}
+
+static mbl_status launch_bapply_staged(mbl_basis_s* b, mbl_batch_s* w, const BatchDev& Q,
+                                       const double* x, double* y, hipStream_t s) {
+  MBL_TRY(staged_plan(b, w, s));
+  const DevBasis B = b->dev();
+  const StagedBlock* blk = static_cast<const StagedBlock*>(w->stage_blocks);
+  switch (b->L) {
+    case 14:
+      hipLaunchKernelGGL(k_bapply_staged<14>, dim3(w->stage_G), dim3(kBWG), 0, s, B, Q, blk,
+                         w->stage_first, x, y);
+      break;
+    case 16:
+      hipLaunchKernelGGL(k_bapply_staged<16>, dim3(w->stage_G), dim3(kBWG), 0, s, B, Q, blk,
+                         w->stage_first, x, y);
+      break;
+    case 22:
+      hipLaunchKernelGGL(k_bapply_staged<22>, dim3(w->stage_G), dim3(kBWG), 0, s, B, Q, blk,
+                         w->stage_first, x, y);
+      break;
+    default:
+      set_error("internal: no staged instance for this L");
+      return MBL_ERR_ARG;
+  }
+  MBL_HIP(hipGetLastError());
+  return MBL_OK;
+}
+
+}  // namespace mbl
+
 extern "C" {
 
 mbl_status mbl_batch_create(mbl_basis b, int R, int mmax, int nevmax, mbl_batch* out) {
@@ -2051,6 +2341,7 @@ mbl_status mbl_apply_H_batched(mbl_basis b, mbl_batch w, const double* h_host,
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   MBL_TRY(bupload(w, h_host, sigma_host, s));
   BatchDev Q{w->h, w->c0, w->R, w->sched_grid};
+  if (staged_instance(b, w->R)) return launch_bapply_staged(b, w, Q, x_dev, y_dev, s);
   return launch_bapply<double, 0, false>(b, Q, BGivens{}, x_dev, y_dev, nullptr, s);
 }
 

@@ -343,6 +343,7 @@ __device__ __forceinline__ void for_rows(const DevBasis& B, const RowTables& t, 
   X(18, 9)                 \
   X(20, 9)                 \
   X(20, 11)                \
+  X(22, 10)                \
   X(22, 9)                 \
   X(22, 11)                \
   X(24, 9)                 \

@@ -30,7 +30,7 @@ def _batch_inputs(L, R, h=3.0, seed0=0):
     return fields, sig
 
 
-@pytest.mark.parametrize("L,R", [(12, 2), (12, 8), (14, 32), (16, 4), (16, 16)])
+@pytest.mark.parametrize("L,R", [(12, 2), (12, 8), (14, 32), (16, 4), (16, 16), (16, 32)])
 def test_apply_batched_dense_parity(gpu, torch, L, R):
     say(f"apply batched L={L} R={R}")
     b = gpu.Basis(L)
@@ -60,13 +60,15 @@ def test_apply_batched_f32(gpu, torch):
         assert np.abs(Y[:, r] - yref).max() <= 2e-6 * np.abs(yref).max()
 
 
-@pytest.mark.parametrize("L,R,split", [(22, 32, "tuned"), (22, 32, "default"), (24, 8, "default")])
+@pytest.mark.parametrize("L,R,split", [(22, 32, "tuned"), (22, 32, "default"), (22, 32, "staged"),
+                                       (24, 8, "default")])
 def test_apply_batched_sampled_rows_large(gpu, torch, L, R, split):
     """Full-size batched launches, rows checked one by one by the oracle; the
     tuned split at L=22, R=32 is the launch the benchmark times (with the
-    bench's fields: h = 3.5, seeds 0..31)."""
+    bench's fields: h = 3.5, seeds 0..31); split 10 at R = 32 takes the
+    block-staged product."""
     from paper_2203_09732_amd import tune
-    lo = tune.best_lo_bits(L, R, "fp64") if split == "tuned" else 0
+    lo = {"tuned": tune.best_lo_bits(L, R, "fp64"), "staged": 10}.get(split, 0)
     say(f"apply batched sampled L={L} R={R} lo_bits={lo or 'default'}")
     b = gpu.Basis(L, lo)
     bt = gpu.Batch(b, R)
@@ -211,3 +213,21 @@ def test_si_lanczos_batched_frozen_realization_with_poisoned_memory(gpu, torch):
         H = model.hamiltonian_dense(L, fields[r])
         E, _ = lanczos.eigenpairs_dense(H, sig[r], nev)
         assert np.all(np.abs(res.evals[r] - E) / np.maximum(np.abs(E), 1) <= 1e-10)
+
+
+def test_staged_product_matches_row_product(gpu, torch):
+    """The block-staged product (split 10, R = 32) against the row product at
+    another split, on the same full-size L = 22 input: the same terms summed
+    in another order, so equal to rounding."""
+    L, R = 22, 32
+    fields, sig = _batch_inputs(L, R, h=3.5)
+    out = {}
+    for lo in (10, 11):
+        b = gpu.Basis(L, lo)
+        bt = gpu.Batch(b, R)
+        X = torch.randn((b.n, R), dtype=torch.float64, device="cuda",
+                        generator=torch.Generator(device="cuda").manual_seed(5))
+        out[lo] = gpu.apply_H_batched(b, bt, fields, sig, X)
+    d = (out[10] - out[11]).abs().max().item()
+    say(f"  staged vs row product: max |dy| = {d:.2e}")
+    assert d <= 1e-14 * out[11].abs().max().item()
