@@ -13,7 +13,7 @@ whole step; the roofline object reports the same figure against the HBM
 peak. Time per MINRES iteration at L=22 (FP64 and FP32-inner) and seconds
 per converged eigenpair are reported beside it: measured at L=18 (the
 largest chain whose eigen-runs fit the bench's few minutes; one FP64 pair at
-L=22 takes about three minutes, see DESIGN.md) in the single, batched and
+L=22 takes about three minutes) in the single, batched and
 FP32-inner forms, and at L=14 (the plain 10-pair workload) for comparison
 with the oracle's dense solver on the host.
 

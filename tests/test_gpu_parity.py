@@ -1,6 +1,6 @@
 """Parity of the HIP path against the CPU oracle, through the C ABI.
 
-Tolerances (derived in DESIGN.md, "Parity bar"):
+Tolerances (each derived from the arithmetic of the two sides):
 * indexing (states, ranks): bit-exact;
 * apply_H / preconditioner in FP64: |y - y_ref| <= 1e-13 max|y_ref| (the two
   sides sum the diagonal in different orders);
