@@ -322,12 +322,18 @@ __device__ __forceinline__ double2 bld_nt(__amdgpu_buffer_rsrc_t r, uint32_t v, 
 
 typedef __attribute__((address_space(3))) void lds_void_t;
 
-template <int L>
-__global__ __launch_bounds__(kBWG) void k_bapply_staged(DevBasis B, BatchDev Q,
+// MODE 1 is the product of MINRES iteration k, as k_bapply<double, 1, true>:
+// the Givens step of iteration k - 1 first (every workgroup the same, stored
+// by workgroup 0), realization pairs that are then both done skipped, and
+// per-workgroup partial sums of x . y per realization (the grid is the row
+// kernels' grid, so the next kernels read as many partials).
+template <int L, int MODE>
+__global__ __launch_bounds__(kBWG) void k_bapply_staged(DevBasis B, BatchDev Q, BGivens gv,
                                                         const StagedBlock* __restrict__ blocks,
                                                         const int* __restrict__ wg_first,
                                                         const double* __restrict__ x,
-                                                        double* __restrict__ y) {
+                                                        double* __restrict__ y,
+                                                        double* __restrict__ partials) {
   constexpr int NLO = kStageNlo, R = kStageR, NHI = L - NLO;
   constexpr int PR = R / 2, RPW = 64 / PR, ROWB = R * 8, NW = kBWG / 64;
   constexpr int NNIB = (NLO + 3) / 4;
@@ -340,9 +346,29 @@ __global__ __launch_bounds__(kBWG) void k_bapply_staged(DevBasis B, BatchDev Q,
   __shared__ __align__(16) double s_fA[R];                // high-bit field sum of a block
   __shared__ __align__(16) double s_fB[R];
   __shared__ __align__(16) double s_h[R * L];
+  __shared__ double s_red[MODE == 1 ? NW * R : 1];
+  __shared__ double s_done[MODE == 1 ? R : 1];
   const int tid = threadIdx.x, lane = tid & 63;
   const uint32_t wave = uni(tid >> 6);
   const int first = wg_first[blockIdx.x], last = wg_first[blockIdx.x + 1];
+  if (MODE == 1) {
+    if (gv.active) {
+      BState sp{};
+      double al = 0.0;
+      if (tid < R) {
+        sp = gv.Sprev[tid];
+        al = gv.alpha[tid];
+      }
+      const double qz = bsum_partials(gv.part2, gv.G, R, s_red);
+      if (tid < R) {
+        const BState so = bgivens_step(sp, al, qz, gv.tol, gv.kmax);
+        if (blockIdx.x == 0) gv.Scur[tid] = so;
+        s_done[tid] = so.done ? 1.0 : 0.0;
+      }
+    } else if (tid < R) {
+      s_done[tid] = gv.Scur[tid].done ? 1.0 : 0.0;
+    }
+  }
   for (int t = tid; t < (1 << NLO); t += kBWG) {
     s_rank[t] = B.lo_rank[t];
     s_state[t] = B.lo_state[t];
@@ -378,7 +404,10 @@ __global__ __launch_bounds__(kBWG) void k_bapply_staged(DevBasis B, BatchDev Q,
       fh[tid] = f;
     }
   };
+  double acc0 = 0.0, acc1 = 0.0;   // MODE 1: x . y of this lane's pair
+  bool live = true;
   auto compute = [&](const StagedBlock& o, const double* buf, const double* fh) {
+    if (!live) return;
     const uint32_t hi = uni(o.hi), cnt = uni(o.cnt), coff = uni(o.coff);
     const uint32_t sb_bnd = uni(o.sb_bnd), sb_wrap = uni(o.sb_wrap);
     uint32_t sbh[NHI - 1];
@@ -442,10 +471,24 @@ __global__ __launch_bounds__(kBWG) void k_bapply_staged(DevBasis B, BatchDev Q,
       yv.x = d0 * own.x + 0.5 * a0;
       yv.y = d1 * own.y + 0.5 * a1;
       BIO<double>::st<kStoreStream>(yv, ry, (uni(o.row0) + j) * ROWB + loff, 0);
+      if (MODE == 1) {
+        acc0 += own.x * yv.x;
+        acc1 += own.y * yv.y;
+      }
     }
   };
   __syncthreads();
-  if (first >= last) return;
+  if (MODE == 1) {
+    const int lp = lane % PR;
+    live = !(s_done[2 * lp] != 0.0 && s_done[2 * lp + 1] != 0.0);
+  }
+  if (first >= last) {
+    if (MODE == 1) {   // no blocks: zero partials
+      const double sm = bblock_sum(0.0, 0.0, s_red, R);
+      if (tid < R) partials[(size_t)blockIdx.x * R + tid] = sm;
+    }
+    return;
+  }
   stage(blocks[first], bufA, s_fA);
   for (int i = first; i < last; i += 2) {
     __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this wave's DMA into the buffer landed
@@ -457,6 +500,11 @@ __global__ __launch_bounds__(kBWG) void k_bapply_staged(DevBasis B, BatchDev Q,
     __syncthreads();
     if (i + 2 < last) stage(blocks[i + 2], bufA, s_fA);
     compute(blocks[i + 1], bufB, s_fB);
+  }
+  if (MODE == 1) {
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // no DMA left in flight past the kernel's end
+    const double sm = bblock_sum(acc0, acc1, s_red, R);
+    if (tid < R) partials[(size_t)blockIdx.x * R + tid] = sm;
   }
 }
 
@@ -1054,6 +1102,128 @@ static mbl_status breduce_host(mbl_batch_s* bw, const double* partials, int G, i
   return MBL_OK;
 }
 
+static bool staged_instance(const mbl_basis_s* b, int R) {
+  return R == kStageR && b->nlo == kStageNlo && (b->L == 14 || b->L == 16 || b->L == 22);
+}
+
+// The staged product's block lists for the workspace's grid: the blocks of
+// one eighth of the rows go to the workgroups of one XCD (workgroup g runs on
+// XCD g % 8), each block to that XCD's workgroup with the fewest rows so far.
+static mbl_status staged_plan(mbl_basis_s* b, mbl_batch_s* w, hipStream_t s) {
+  // the row kernels' grid, so that the MINRES product's partial sums are as
+  // many as the kernels after it read
+  const int G = bgrid(b, w->R, w->sched_grid);
+  if (w->stage_blocks && w->stage_G == G) return MBL_OK;
+  if (w->stage_blocks) (void)hipFree(w->stage_blocks);
+  if (w->stage_first) (void)hipFree(w->stage_first);
+  w->stage_blocks = nullptr;
+  w->stage_first = nullptr;
+  const int nhi = b->nhi, nlo = b->nlo;
+  std::vector<uint32_t> hi_off((size_t)1 << nhi), coff(nlo + 2);
+  MBL_HIP(hipMemcpyAsync(hi_off.data(), b->d_hi_off, sizeof(uint32_t) * hi_off.size(),
+                         hipMemcpyDeviceToHost, s));
+  MBL_HIP(hipMemcpyAsync(coff.data(), b->d_lo_coff, sizeof(uint32_t) * coff.size(),
+                         hipMemcpyDeviceToHost, s));
+  MBL_HIP(hipStreamSynchronize(s));
+  struct Blk {
+    uint32_t hi, row0, cnt, coff;
+  };
+  std::vector<Blk> all;
+  for (size_t hi = 0; hi < hi_off.size(); ++hi) {
+    if (hi_off[hi] == 0xffffffffu) continue;
+    const int c = b->half - __builtin_popcountll(hi);
+    if (c < 0 || c > nlo) continue;
+    const uint32_t cnt = coff[c + 1] - coff[c];
+    if (cnt == 0) continue;
+    if (cnt > (uint32_t)kStageCap) {
+      set_error("internal: staged block larger than its LDS buffer");
+      return MBL_ERR_NUMERIC;
+    }
+    all.push_back(Blk{(uint32_t)hi, hi_off[hi], cnt, coff[c]});
+  }
+  const int X = kXcds, per = std::max(1, G / X);
+  std::vector<std::vector<Blk>> wl(G);
+  const uint64_t n = (uint64_t)b->n;
+  size_t bi = 0;
+  for (int xcd = 0; xcd < X; ++xcd) {
+    const uint64_t lim = n * (uint64_t)(xcd + 1) / X;
+    std::vector<uint64_t> load(per, 0);
+    while (bi < all.size() && (all[bi].row0 < lim || xcd == X - 1)) {
+      int best = 0;
+      for (int q = 1; q < per; ++q)
+        if (load[q] < load[best]) best = q;
+      load[best] += all[bi].cnt;
+      wl[std::min(G - 1, xcd + X * best)].push_back(all[bi]);
+      ++bi;
+    }
+  }
+  std::vector<StagedBlock> list;
+  std::vector<int> first(1, 0);
+  const uint32_t ROWB = kStageR * 8;
+  for (int g = 0; g < G; ++g) {
+    for (const Blk& v : wl[g]) {
+      StagedBlock d{};
+      d.hi = v.hi;
+      d.row0 = v.row0;
+      d.cnt = v.cnt;
+      d.coff = v.coff;
+      // neighbour blocks that do not exist are only addressed by masked gathers
+      d.sb_bnd = hi_off[v.hi ^ 1u] * ROWB;
+      d.sb_wrap = hi_off[v.hi ^ (1u << (nhi - 1))] * ROWB;
+      for (int bb = 0; bb + 1 < nhi; ++bb) d.sbh[bb] = hi_off[v.hi ^ (3u << bb)] * ROWB;
+      list.push_back(d);
+    }
+    first.push_back((int)list.size());
+  }
+  if (hipMalloc(&w->stage_blocks, sizeof(StagedBlock) * std::max<size_t>(list.size(), 1)) !=
+          hipSuccess ||
+      hipMalloc((void**)&w->stage_first, sizeof(int) * first.size()) != hipSuccess) {
+    (void)hipGetLastError();
+    set_error("device allocation failed (staged block lists)");
+    return MBL_ERR_NOMEM;
+  }
+  MBL_HIP(hipMemcpyAsync(w->stage_blocks, list.data(), sizeof(StagedBlock) * list.size(),
+                         hipMemcpyHostToDevice, s));
+  MBL_HIP(hipMemcpyAsync(w->stage_first, first.data(), sizeof(int) * first.size(),
+                         hipMemcpyHostToDevice, s));
+  MBL_HIP(hipStreamSynchronize(s));
+  w->stage_G = G;
+  return MBL_OK;
+}
+
+// The staged product; its block lists must exist (staged_plan, which
+// synchronizes and so runs before any graph capture).
+template <int MODE>
+static mbl_status launch_bapply_staged(mbl_basis_s* b, mbl_batch_s* w, const BatchDev& Q,
+                                       const BGivens& gv, const double* x, double* y,
+                                       double* partials, hipStream_t s) {
+  if (!w->stage_blocks || w->stage_G != bgrid(b, w->R, w->sched_grid)) {
+    set_error("internal: staged product launched without its block lists");
+    return MBL_ERR_ARG;
+  }
+  const DevBasis B = b->dev();
+  const StagedBlock* blk = static_cast<const StagedBlock*>(w->stage_blocks);
+  switch (b->L) {
+    case 14:
+      hipLaunchKernelGGL((k_bapply_staged<14, MODE>), dim3(w->stage_G), dim3(kBWG), 0, s, B, Q,
+                         gv, blk, w->stage_first, x, y, partials);
+      break;
+    case 16:
+      hipLaunchKernelGGL((k_bapply_staged<16, MODE>), dim3(w->stage_G), dim3(kBWG), 0, s, B, Q,
+                         gv, blk, w->stage_first, x, y, partials);
+      break;
+    case 22:
+      hipLaunchKernelGGL((k_bapply_staged<22, MODE>), dim3(w->stage_G), dim3(kBWG), 0, s, B, Q,
+                         gv, blk, w->stage_first, x, y, partials);
+      break;
+    default:
+      set_error("internal: no staged instance for this L");
+      return MBL_ERR_ARG;
+  }
+  MBL_HIP(hipGetLastError());
+  return MBL_OK;
+}
+
 // The streaming form's view of a running batched MINRES. After each chunk of
 // iterations has been issued, the hook receives the states after iteration
 // `iter` of an earlier chunk (the snapshot lags one chunk, so the d/x updates
@@ -1121,9 +1291,17 @@ static mbl_status bminres_core(mbl_basis_s* b, mbl_batch_s* bw, const BatchDev& 
   // (and skips realizations that are then done), and the z/q update, which
   // first forms alpha_k. The d/x update of iterations k - 4 .. k - 1 runs
   // between them once their Givens steps are known.
+  // FP64 products at split 10 with R = 32 run block-staged (the block lists
+  // are built here, outside any graph capture)
+  const bool staged = std::is_same<T, double>::value && staged_instance(b, R);
+  if (staged) MBL_TRY(staged_plan(b, bw, s));
   auto iteration = [&](int64_t k, hipStream_t st) -> mbl_status {
     const BGivens gv = givens_args(k);
-    MBL_TRY((launch_bapply<T, 1, true>(b, Q, gv, Qv[k % kRing], P, bw->partials1, st)));
+    if (staged)
+      MBL_TRY(launch_bapply_staged<1>(b, bw, Q, gv, (const double*)Qv[k % kRing], (double*)P,
+                                      bw->partials1, st));
+    else
+      MBL_TRY((launch_bapply<T, 1, true>(b, Q, gv, Qv[k % kRing], P, bw->partials1, st)));
     if (k > dxg && (k - 1) % dxg == 0) MBL_TRY(dx_group(k - dxg, dxg, st));
     MBL_TRY(launch_bzq<T>(b, Q, precond, gv.Scur, bw->partials1, bw->alph + (k & 1) * R, P,
                           Z[k & 1], Z[(k + 1) & 1], Qv[(k + 1) % kRing], bw->partials2, st));
@@ -2162,123 +2340,6 @@ static bool pow2(int R) { return R >= 2 && R <= kBMaxR && (R & (R - 1)) == 0; }
 
 using namespace mbl;
 
-namespace mbl {
-
-static bool staged_instance(const mbl_basis_s* b, int R) {
-  return R == kStageR && b->nlo == kStageNlo && (b->L == 14 || b->L == 16 || b->L == 22);
-}
-
-// The staged product's block lists for the workspace's grid: the blocks of
-// one eighth of the rows go to the workgroups of one XCD (workgroup g runs on
-// XCD g % 8), each block to that XCD's workgroup with the fewest rows so far.
-static mbl_status staged_plan(mbl_basis_s* b, mbl_batch_s* w, hipStream_t s) {
-  const int G = w->sched_grid > 0 ? w->sched_grid : std::max(8, device_cus(b->device) / 8 * 8);
-  if (w->stage_blocks && w->stage_G == G) return MBL_OK;
-  if (w->stage_blocks) (void)hipFree(w->stage_blocks);
-  if (w->stage_first) (void)hipFree(w->stage_first);
-  w->stage_blocks = nullptr;
-  w->stage_first = nullptr;
-  const int nhi = b->nhi, nlo = b->nlo;
-  std::vector<uint32_t> hi_off((size_t)1 << nhi), coff(nlo + 2);
-  MBL_HIP(hipMemcpyAsync(hi_off.data(), b->d_hi_off, sizeof(uint32_t) * hi_off.size(),
-                         hipMemcpyDeviceToHost, s));
-  MBL_HIP(hipMemcpyAsync(coff.data(), b->d_lo_coff, sizeof(uint32_t) * coff.size(),
-                         hipMemcpyDeviceToHost, s));
-  MBL_HIP(hipStreamSynchronize(s));
-  struct Blk {
-    uint32_t hi, row0, cnt, coff;
-  };
-  std::vector<Blk> all;
-  for (size_t hi = 0; hi < hi_off.size(); ++hi) {
-    if (hi_off[hi] == 0xffffffffu) continue;
-    const int c = b->half - __builtin_popcountll(hi);
-    if (c < 0 || c > nlo) continue;
-    const uint32_t cnt = coff[c + 1] - coff[c];
-    if (cnt == 0) continue;
-    if (cnt > (uint32_t)kStageCap) {
-      set_error("internal: staged block larger than its LDS buffer");
-      return MBL_ERR_NUMERIC;
-    }
-    all.push_back(Blk{(uint32_t)hi, hi_off[hi], cnt, coff[c]});
-  }
-  const int X = kXcds, per = G / X;
-  std::vector<std::vector<Blk>> wl(G);
-  const uint64_t n = (uint64_t)b->n;
-  size_t bi = 0;
-  for (int xcd = 0; xcd < X; ++xcd) {
-    const uint64_t lim = n * (uint64_t)(xcd + 1) / X;
-    std::vector<uint64_t> load(per, 0);
-    while (bi < all.size() && (all[bi].row0 < lim || xcd == X - 1)) {
-      int best = 0;
-      for (int q = 1; q < per; ++q)
-        if (load[q] < load[best]) best = q;
-      load[best] += all[bi].cnt;
-      wl[xcd + X * best].push_back(all[bi]);
-      ++bi;
-    }
-  }
-  std::vector<StagedBlock> list;
-  std::vector<int> first(1, 0);
-  const uint32_t ROWB = kStageR * 8;
-  for (int g = 0; g < G; ++g) {
-    for (const Blk& v : wl[g]) {
-      StagedBlock d{};
-      d.hi = v.hi;
-      d.row0 = v.row0;
-      d.cnt = v.cnt;
-      d.coff = v.coff;
-      // neighbour blocks that do not exist are only addressed by masked gathers
-      d.sb_bnd = hi_off[v.hi ^ 1u] * ROWB;
-      d.sb_wrap = hi_off[v.hi ^ (1u << (nhi - 1))] * ROWB;
-      for (int bb = 0; bb + 1 < nhi; ++bb) d.sbh[bb] = hi_off[v.hi ^ (3u << bb)] * ROWB;
-      list.push_back(d);
-    }
-    first.push_back((int)list.size());
-  }
-  if (hipMalloc(&w->stage_blocks, sizeof(StagedBlock) * std::max<size_t>(list.size(), 1)) !=
-          hipSuccess ||
-      hipMalloc((void**)&w->stage_first, sizeof(int) * first.size()) != hipSuccess) {
-    (void)hipGetLastError();
-    set_error("device allocation failed (staged block lists)");
-    return MBL_ERR_NOMEM;
-  }
-  MBL_HIP(hipMemcpyAsync(w->stage_blocks, list.data(), sizeof(StagedBlock) * list.size(),
-                         hipMemcpyHostToDevice, s));
-  MBL_HIP(hipMemcpyAsync(w->stage_first, first.data(), sizeof(int) * first.size(),
-                         hipMemcpyHostToDevice, s));
-  MBL_HIP(hipStreamSynchronize(s));
-  w->stage_G = G;
-  return MBL_OK;
-}
-
-static mbl_status launch_bapply_staged(mbl_basis_s* b, mbl_batch_s* w, const BatchDev& Q,
-                                       const double* x, double* y, hipStream_t s) {
-  MBL_TRY(staged_plan(b, w, s));
-  const DevBasis B = b->dev();
-  const StagedBlock* blk = static_cast<const StagedBlock*>(w->stage_blocks);
-  switch (b->L) {
-    case 14:
-      hipLaunchKernelGGL(k_bapply_staged<14>, dim3(w->stage_G), dim3(kBWG), 0, s, B, Q, blk,
-                         w->stage_first, x, y);
-      break;
-    case 16:
-      hipLaunchKernelGGL(k_bapply_staged<16>, dim3(w->stage_G), dim3(kBWG), 0, s, B, Q, blk,
-                         w->stage_first, x, y);
-      break;
-    case 22:
-      hipLaunchKernelGGL(k_bapply_staged<22>, dim3(w->stage_G), dim3(kBWG), 0, s, B, Q, blk,
-                         w->stage_first, x, y);
-      break;
-    default:
-      set_error("internal: no staged instance for this L");
-      return MBL_ERR_ARG;
-  }
-  MBL_HIP(hipGetLastError());
-  return MBL_OK;
-}
-
-}  // namespace mbl
-
 extern "C" {
 
 mbl_status mbl_batch_create(mbl_basis b, int R, int mmax, int nevmax, mbl_batch* out) {
@@ -2341,7 +2402,10 @@ mbl_status mbl_apply_H_batched(mbl_basis b, mbl_batch w, const double* h_host,
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   MBL_TRY(bupload(w, h_host, sigma_host, s));
   BatchDev Q{w->h, w->c0, w->R, w->sched_grid};
-  if (staged_instance(b, w->R)) return launch_bapply_staged(b, w, Q, x_dev, y_dev, s);
+  if (staged_instance(b, w->R)) {
+    MBL_TRY(staged_plan(b, w, s));
+    return launch_bapply_staged<0>(b, w, Q, BGivens{}, x_dev, y_dev, nullptr, s);
+  }
   return launch_bapply<double, 0, false>(b, Q, BGivens{}, x_dev, y_dev, nullptr, s);
 }
 

@@ -231,3 +231,32 @@ def test_staged_product_matches_row_product(gpu, torch):
     d = (out[10] - out[11]).abs().max().item()
     say(f"  staged vs row product: max |dy| = {d:.2e}")
     assert d <= 1e-14 * out[11].abs().max().item()
+
+
+def test_staged_minres_product(gpu, torch):
+    """Batched MINRES at L = 14, R = 32 (split 10: the block-staged product
+    with the Givens prologue and partial sums) against dense solves, and
+    against the row product at split 7 on the same right-hand sides (the same
+    recurrence with sums in another order)."""
+    L, R = 14, 32
+    fields = [disorder_fields(L, 3.0, 60 + r) for r in range(R)]
+    sig = [0.03 * r - 0.5 for r in range(R)]
+    n = len(model.sector_states(L))
+    B = np.stack([gaussian_vector(n, 160 + r) for r in range(R)], axis=1)
+    B /= np.linalg.norm(B, axis=0)
+    out = {}
+    for lo in (10, 7):
+        b = gpu.Basis(L, lo)
+        bt = gpu.Batch(b, R)
+        x, its, phi, st = gpu.minres_solve_batched(b, bt, fields, sig,
+                                                   torch.as_tensor(B, device="cuda"), tol=1e-12)
+        assert st == 0 and np.all(phi < 1e-12)
+        out[lo] = (x.cpu().numpy(), its)
+    X10, its10 = out[10]
+    X7, its7 = out[7]
+    say(f"  staged iterations {list(its10[:6])}..., row product {list(its7[:6])}...")
+    for r in (0, 13, 31):
+        xd = minres.solve_dense(model.hamiltonian_dense(L, fields[r]), sig[r], B[:, r])
+        assert np.linalg.norm(X10[:, r] - xd) / np.linalg.norm(xd) <= 1e-8
+    assert np.max(np.linalg.norm(X10 - X7, axis=0) / np.linalg.norm(X7, axis=0)) <= 1e-8
+    assert np.all(np.abs(its10 - its7) <= 0.1 * its7 + 5)

@@ -54,10 +54,12 @@ def test_campaign_uneven_lengths_and_resume(gpu, torch, tmp_path, mode):
     assert len(open(path).read().strip().splitlines()) == 6
 
 
-def test_batched_minres_graph_replays_match_eager(gpu, torch):
+@pytest.mark.parametrize("R", [8, 32])
+def test_batched_minres_graph_replays_match_eager(gpu, torch, R):
     """Several solves with graph replays, with eager work and syncs between
-    them; each must equal the eager-launch result bit for bit."""
-    L, R = 14, 8
+    them; each must equal the eager-launch result bit for bit (R = 32 at
+    L = 14 runs the block-staged MINRES product)."""
+    L = 14
     b = gpu.Basis(L)
     fields = [disorder_fields(L, 3.0, 200 + r) for r in range(R)]
     sig = [0.05 * r - 0.2 for r in range(R)]
