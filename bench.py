@@ -66,7 +66,7 @@ def headline_kernel(L: int, lo_bits: int, R: int) -> str:
     block-staged one for split 10 at R = 32 (L = 14, 16, 22), else the row
     product of the split."""
     if lo_bits == 10 and R == 32 and L in (14, 16, 22):
-        return f"k_bapply_staged<{L}>"
+        return f"k_bapply_staged<{L},0>"
     return f"k_bapply<double,0,false,{L},{lo_bits}>"
 
 
