@@ -292,7 +292,11 @@ mbl_status mbl_batch_bytes(mbl_batch w, int64_t* bytes);
  * MBL_ERR_ARG on other values. Drops the workspace's captured graphs when the
  * schedule changes. */
 mbl_status mbl_batch_set_schedule(mbl_batch w, int grid, int graph_iters, int dx_group);
-/* y_r = (H_r - sigma_r) x_r for every r (Eq. (1)); interleaved x, y. Async. */
+/* y_r = (H_r - sigma_r) x_r for every r (Eq. (1)); interleaved x, y. Async.
+ * At lo_bits = 10 with R = 32 (L = 14, 16, 22) the product stages blocks of
+ * x in LDS; the first such call on a workspace (and the first after a
+ * schedule change) builds the workspace's block lists and synchronizes the
+ * stream once. */
 mbl_status mbl_apply_H_batched(mbl_basis b, mbl_batch w, const double* h_host,
                                const double* sigma_host, const double* x_dev, double* y_dev,
                                void* stream);

@@ -293,10 +293,11 @@ __global__ void k_binit_state(const double* __restrict__ partials, int G, int R,
   }
 }
 
-// ---- block-staged plain product (split nlo = 10, R = 32) ---------------------
-// y_r = (H_r - sigma_r) x_r with the per-row arithmetic of k_bapply<double,
-// 0, false> (the same terms in the same order), for bases split at nlo = 10
-// (a hi block holds at most C(10, 5) = 252 rows, 252 x 256 B of x at R = 32).
+// ---- block-staged product (split nlo = 10, R = 32, FP64) --------------------
+// y_r = (H_r - sigma_r) x_r with the terms of k_bapply<double, 0, false>
+// (the off-diagonal ones summed in another order: low bonds, split bond, high
+// bonds, wrap bond), for bases split at nlo = 10 (a hi block holds at most
+// C(10, 5) = 252 rows, 252 x 256 B of x at R = 32).
 // Each workgroup owns a host-built list of whole blocks: the blocks of one
 // eighth of the rows go to that eighth's XCD, balanced by rows between its
 // workgroups. While it computes block i, the workgroup stages block i + 1 of x
