@@ -47,6 +47,51 @@ def test_tuner_cache_key_and_default(pkg, monkeypatch, tmp_path):
     assert tune.best_lo_bits(22, 32, "fp64") == 0       # other architecture
 
 
+def test_tuner_schedule_entries(pkg, monkeypatch, tmp_path):
+    """Cached schedules: the four knobs of a full entry, zeros (library
+    defaults) for entries from before the schedule knobs and for unknown keys;
+    apply_schedule hands them to the batch."""
+    from paper_2203_09732_amd import tune
+    cache = tmp_path / "tuning.json"
+    cache.write_text(json.dumps({"gfx950": {
+        "L22_R32_fp64": {"lo_bits": 10, "grid": 256, "graph_iters": 8, "dx_group": 4},
+        "L26_R16_fp64": {"lo_bits": 13}}}))
+    monkeypatch.setattr(tune, "CACHE", str(cache))
+    monkeypatch.setattr(tune, "_arch", lambda: "gfx950")
+    assert tune.best_schedule(22, 32) == (256, 8, 4)
+    assert tune.best_schedule(26, 16) == (0, 0, 0)
+    assert tune.best_schedule(18, 32) == (0, 0, 0)
+
+    class FakeBatch:
+        def set_schedule(self, *knobs):
+            self.knobs = knobs
+    fb = FakeBatch()
+    tune.apply_schedule(fb, 22, 32)
+    assert fb.knobs == (256, 8, 4)
+
+
+def test_bench_names_the_kernel_it_times():
+    import bench
+    assert bench.headline_kernel(22, 10, 32) == "k_bapply_staged<22,0>"
+    assert bench.headline_kernel(22, 11, 32) == "k_bapply<double,0,false,22,11>"
+    assert bench.headline_kernel(22, 10, 16) == "k_bapply<double,0,false,22,10>"
+
+
+def test_committed_tuning_cache_is_well_formed():
+    """Every entry of the committed cache names a split the tuner could pick
+    and schedule values the library accepts."""
+    import os
+    from paper_2203_09732_amd import tune
+    data = json.load(open(os.path.join(os.path.dirname(tune.__file__), "tuning.json")))
+    for arch, entries in data.items():
+        for key, e in entries.items():
+            L = int(key.split("_")[0][1:])
+            assert e["lo_bits"] in tune.CANDIDATES[L], (key, e)
+            assert e.get("grid", 0) in (0,) + tuple(g for g in tune.GRIDS if g)
+            assert e.get("graph_iters", 16) in tune.GRAPH_ITERS
+            assert e.get("dx_group", 4) in tune.DX_GROUPS
+
+
 def test_bench_host_report_and_no_projection():
     import bench
     info = bench.host_info()
