@@ -430,7 +430,7 @@ _sig("mbl_twist_expect_batched", _i32, [_vp, _vp, _vp, C.c_int, _dp, _vp])
 
 
 class Batch:
-    """Workspace for R realizations of one L solved in lockstep. Batched
+    """Workspace for R realizations of one L solved together. Batched
     vectors are (n, R) row-major tensors: element (i, r) at i * R + r."""
 
     def __init__(self, basis: Basis, R: int, mmax: int = 0, nevmax: int = 0):

@@ -6,8 +6,9 @@ Two ways to run them:
   call (mbl_si_lanczos_problems) in chunks of up to ``chunk`` realizations of
   any mix of L; realizations with L <= 16 are solved in one persistent launch
   per chunk, a workgroup per realization, sigma = (E_min + E_max)/2
-  (Sec. IV A) included, and the longer ones in lockstep batches of up to 32
-  inside the same call;
+  (Sec. IV A) included, and the longer ones in streaming batches of up to 32
+  lanes inside the same call (each lane runs its own realization's Lanczos
+  steps and takes the next realization when its own has converged);
 * ``lockstep``: realizations are grouped by L and each group is solved in
   batches of R realizations (a power of two, as large as the kernels' LDS
   budget allows for that L) by the lockstep shift-invert Lanczos, after sigma

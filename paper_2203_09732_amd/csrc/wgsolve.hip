@@ -16,7 +16,8 @@
 // had mostly not finished after 800 s, where a lockstep batch of 32 (whose
 // interleaved layout turns each gather into 256 contiguous bytes) takes
 // about 7 s of the whole chip per realization. Longer chains therefore go to
-// the lockstep batches inside the same call. The solver is inlined into the
+// the batched form inside the same call: 32 streaming lanes, each running its
+// own realization's Lanczos steps (batched.hip). The solver is inlined into the
 // kernel for each chain length (the problem's basis selects the instance), so
 // every problem-wide value stays in scalar registers; it needs 229 VGPRs, so
 // a workgroup is 512 threads and a CU runs one.
