@@ -34,6 +34,33 @@ def test_campaign_resume_reads_done_indices(pkg, tmp_path):
     assert campaign._done_indices(str(p)) == {3, 7}
 
 
+def test_campaign_persistent_mode_chunks_and_resumes(pkg, monkeypatch, tmp_path):
+    """The driver's problem-array mode with the library call replaced by a
+    stand-in: realizations go in chunks, every one gets a record, and a
+    second run over the same results file calls nothing."""
+    import numpy as np
+    from paper_2203_09732_amd import campaign
+    calls = []
+
+    def fake_problems(problems, **kw):
+        calls.append([p["L"] for p in problems])
+        res = [pkg.ProblemResult(p["L"], 0, np.arange(p["nev"], dtype=float), None,
+                                 np.zeros(p["nev"]), np.zeros(p["nev"], complex), 0.5, 20,
+                                 p["nev"], 1000, 1e-12, 1.0) for p in problems]
+        return 0, res
+    monkeypatch.setattr(campaign, "si_lanczos_problems", fake_problems)
+    tasks = [campaign.Task(i, (14, 16, 18)[i % 3], 3.0, np.zeros((14, 16, 18)[i % 3]))
+             for i in range(5)]
+    out = tmp_path / "c.jsonl"
+    recs = campaign.run(tasks, 2, results_path=str(out), mode="persistent", chunk=3, log=None)
+    assert calls == [[14, 16, 18], [14, 16]]
+    assert sorted(r["index"] for r in recs) == list(range(5))
+    assert all(r["mode"] == "persistent" and r["nconv"] == 2 for r in recs)
+    again = campaign.run(tasks, 2, results_path=str(out), mode="persistent", chunk=3, log=None)
+    assert again == [] and len(calls) == 2
+    assert campaign._done_indices(str(out)) == set(range(5))
+
+
 def test_tuner_cache_key_and_default(pkg, monkeypatch, tmp_path):
     from paper_2203_09732_amd import tune
     assert tune._key(22, 32, "fp64") == "L22_R32_fp64"
